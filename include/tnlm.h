@@ -1,0 +1,181 @@
+/*
+ * tnlm.h -- C ABI of the MI355X (gfx950) TNLM 4DCT reconstruction library.
+ *
+ * Method: Tian, Jia, Dong, Lou, Jiang, "Low-dose 4DCT reconstruction via
+ * temporal non-local means" (arXiv:1009.1351). All N respiratory phases f_i of
+ * one CT slice are reconstructed jointly by minimising Eq. 1: a statistically
+ * weighted data term (P_i f_i - y_i)^T S^-1 (P_i f_i - y_i) plus a temporal
+ * non-local-means term coupling phase i with i-1 and i+1 on a ring of phases
+ * (§2.1). The solver is the modified forward-backward splitting of §2.2:
+ * per outer iteration, M1 CGLS steps on the whitened data term, new patch
+ * weights from the CGLS output (Eq. 8, W x W window of §2.3), M2 Gauss-Jacobi
+ * sweeps of Eq. 7, and a positivity clamp (TNLM algorithm box).
+ *
+ * Conventions shared by every entry point
+ *   - Images: float32, [N][L][L] row-major; row index r along +y, column c
+ *     along +x; pixel (r, c) centre = ((c+1/2) D - L D/2, (r+1/2) D - L D/2),
+ *     D = pixel_mm.
+ *   - Sinograms: float32, [N][V][B] (phase, view, bin), bins contiguous.
+ *   - Geometry (§3): source at sad_mm * (cos th, sin th) for view angle th;
+ *     equiangular arc detector; bin b has fan angle
+ *     g_b = (b - (B-1)/2 + det_offset_bins) * dgamma_rad and its ray leaves
+ *     the source with direction angle th + pi + g_b.
+ *   - w: inverse variances S^-1 (diagonal), float32 [N][V][B], w >= 0.
+ *   - Device pointers ("d_") are caller-owned HIP device memory on the device
+ *     that was current at init; the library never frees or reallocates them.
+ *     Host pointers are read during the call only.
+ *   - All work is enqueued on the HIP stream given at init (a hipStream_t,
+ *     passed as void*; NULL = the default stream). Calls marked "async" return
+ *     before the GPU finishes; the others synchronise that stream once.
+ *   - A context is used by one host thread at a time. Separate contexts on
+ *     separate streams are independent.
+ *   - Errors: every call returns a tnlm_status; 0 = success, < 0 = error
+ *     (nothing is written on argument errors), > 0 = warning. A human-readable
+ *     message of the last failure on the calling thread is returned by
+ *     tnlm_last_error(). No C++ exception crosses this boundary.
+ */
+#ifndef TNLM_H
+#define TNLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TNLM_OK = 0,
+    TNLM_E_INVALID_ARG = -1, /* bad scalar argument or null pointer          */
+    TNLM_E_SHAPE = -2,       /* inconsistent sizes                           */
+    TNLM_E_HIP = -3,         /* a HIP runtime call failed                    */
+    TNLM_E_OOM = -4,         /* device allocation failed                     */
+    TNLM_E_NONFINITE = -5,   /* NaN/Inf detected in inputs or iterates       */
+    TNLM_W_NOT_CONVERGED = 1 /* max_outer reached before tol_rel_update      */
+} tnlm_status;
+
+enum { TNLM_INIT_FBP_ALL = 0, TNLM_INIT_USER = 1 };
+enum { TNLM_SSD_FP32 = 0, TNLM_SSD_BF16_MFMA = 1 };
+
+typedef struct {
+    int32_t n_phases;        /* N >= 1, phases on a ring (§2.1)               */
+    int32_t L;               /* image side, 1 <= L <= 4096                     */
+    double pixel_mm;         /* D > 0                                          */
+    int32_t n_views;         /* V >= 1 per phase                               */
+    int32_t n_bins;          /* B >= 1, B <= 4096                              */
+    double sad_mm;           /* source to rotation centre (541.0 in §3)        */
+    double sdd_mm;           /* source to detector (949.075 in §3)             */
+    double dgamma_rad;       /* angular bin pitch                              */
+    double det_offset_bins;  /* detector offset in bins (e.g. 0.25)            */
+    const double *view_angles_rad; /* host [N][V]; copied at init           */
+} tnlm_geometry;
+
+typedef struct {
+    int32_t patch;           /* d, odd, 3..9: patch side of Eq. 8             */
+    int32_t window;          /* W, odd, 3..21, W <= L: search window (§2.3)    */
+    float h;                 /* > 0: patch-distance scale of Eq. 8            */
+    float mu_hat;            /* >= 0: mu / beta of Eq. 6-7                     */
+    float beta;              /* > 0: FBS constant; used by M1 = 0 and the cost */
+    int32_t m1_cgls;         /* M1 >= 0 CGLS steps (0 = gradient step, Eq. 4)  */
+    int32_t m2_jacobi;       /* M2 >= 1 Gauss-Jacobi sweeps                    */
+    int32_t max_outer;       /* >= 1 outer iterations (cap)                    */
+    float tol_rel_update;    /* stop when ||F^k - F^k-1|| / ||F^k|| < tol; 0 = run max_outer */
+    int32_t init;            /* TNLM_INIT_FBP_ALL or TNLM_INIT_USER            */
+    int32_t ssd_mode;        /* TNLM_SSD_FP32 or TNLM_SSD_BF16_MFMA            */
+} tnlm_params;
+
+typedef struct tnlm_ctx tnlm_ctx;
+
+/*
+ * Create a reconstruction context for one slice (geometry §3, parameters
+ * §2.2-2.3). Builds the per-ray plane tables and allocates all scratch on
+ * the current device. Validates: N >= 1, L >= 1, V >= 1, B >= 1, d and W odd
+ * in range, W <= L, h > 0, mu_hat >= 0, beta > 0, M1 >= 0, M2 >= 1,
+ * max_outer >= 1, tol >= 0. Returns TNLM_E_INVALID_ARG / TNLM_E_SHAPE /
+ * TNLM_E_OOM / TNLM_E_HIP on failure (*out = NULL).
+ */
+tnlm_status tnlm_recon_init(tnlm_ctx **out, const tnlm_geometry *geom, const tnlm_params *params,
+                            void *stream);
+void tnlm_destroy(tnlm_ctx *ctx);
+
+/*
+ * One outer iteration of the TNLM algorithm box (steps 2-5), in place:
+ * d_f holds f^(k-1) on entry and f^(k) on return. d_y, d_w: [N][V][B].
+ * Async. The relative update is recorded on the device (tnlm_get_history).
+ */
+tnlm_status tnlm_step(tnlm_ctx *ctx, const float *d_y, const float *d_w, float *d_f);
+
+/*
+ * Full solve (TNLM algorithm box): f^(0) = FBP of all phases' views
+ * (init = TNLM_INIT_FBP_ALL) or the caller's d_f (TNLM_INIT_USER); then outer
+ * iterations until the relative update falls below tol_rel_update or
+ * max_outer is reached. Synchronises once at the end. out_iters and
+ * out_rel_update (host, nullable) receive the iteration count and the last
+ * relative update. Returns TNLM_W_NOT_CONVERGED when tol > 0 was not reached,
+ * TNLM_E_NONFINITE if an iterate became non-finite.
+ */
+tnlm_status tnlm_solve(tnlm_ctx *ctx, const float *d_y, const float *d_w, float *d_f, int32_t *out_iters,
+                       float *out_rel_update);
+
+/* Relative updates of the iterations done so far by tnlm_solve/tnlm_step
+ * since init (host out[n]; synchronises). Returns the count in *out_n. */
+tnlm_status tnlm_get_history(tnlm_ctx *ctx, float *out, int32_t n, int32_t *out_n);
+
+/* q = P f (Siddon line integrals, §3), all phases. d_f [N][L][L] -> d_q [N][V][B]. Async. */
+tnlm_status tnlm_project(tnlm_ctx *ctx, const float *d_f, float *d_q);
+
+/* f = P^T q, the exact transpose of tnlm_project (Eq. 4, CGLS box). Async. */
+tnlm_status tnlm_backproject(tnlm_ctx *ctx, const float *d_q, float *d_f);
+
+/*
+ * Filtered back-projection (TNLM box, step 1): equiangular fan-beam ramp
+ * filter and distance-weighted back-projection over a full turn. all_phases
+ * != 0: one image from the union of all N*V views, written to every phase
+ * slot of d_f; 0: each phase from its own V views. Async.
+ */
+tnlm_status tnlm_fbp(tnlm_ctx *ctx, const float *d_y, float *d_f, int32_t all_phases);
+
+/*
+ * Data step of §2.2: M1 CGLS steps (CGLS box) on P_n = S^-1/2 P from
+ * u0 = d_f, or the gradient step of Eq. 4 when M1 = 0; d_g <- g^(k).
+ * d_f and d_g must not alias. Async.
+ */
+tnlm_status tnlm_data_step(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, float *d_g);
+
+/*
+ * One Gauss-Jacobi sweep of Eq. 7 with Eq. 8 weights:
+ *   out_i(x) = g_i(x)/(1+mu) + mu/(2mu+2) * sum_{j=i-1,i+1} sum_y w_ij(x,y) value_j(y)
+ * with w_ij computed from the guide stack (patch d, window W, h). clamp != 0
+ * applies max(., 0). All stacks [N][L][L]; d_out must not alias the inputs.
+ * For M2 = 1, guide = value = g. Async.
+ */
+tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, const float *d_value, const float *d_g,
+                            float *d_out, int32_t clamp);
+
+/*
+ * Kernel timing (tracing). While enabled, every kernel the context enqueues
+ * is bracketed by a pair of HIP events recorded on the context's stream, and
+ * tnlm_timing_read returns, per kernel kind, the summed event-to-event time
+ * in milliseconds and the number of launches since the last read (it
+ * synchronises the stream and resets the records). Enabling adds two event
+ * records per launch; disable it outside measurements.
+ */
+enum {
+    TNLM_KIND_PROJECT = 0,     /* forward projector (all modes)               */
+    TNLM_KIND_BACKPROJECT = 1, /* transpose                                   */
+    TNLM_KIND_REGULARIZE = 2,  /* weights + Gauss-Jacobi sweep                */
+    TNLM_KIND_VECTOR = 3,      /* CGLS vector updates, copies                 */
+    TNLM_KIND_FBP = 4,         /* filter + back-projection of the FBP         */
+    TNLM_KIND_OTHER = 5,       /* reductions, checks                          */
+    TNLM_KIND_COUNT = 6
+};
+tnlm_status tnlm_timing_enable(tnlm_ctx *ctx, int32_t enable);
+tnlm_status tnlm_timing_read(tnlm_ctx *ctx, double *ms /* [TNLM_KIND_COUNT] */,
+                             int32_t *launches /* [TNLM_KIND_COUNT] */);
+
+const char *tnlm_status_string(tnlm_status s);
+const char *tnlm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNLM_H */

@@ -1,0 +1,35 @@
+// Small device helpers: deterministic block reductions and launch checks.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tnlm {
+
+constexpr int kBlock = 256;
+
+// Sum of one double per thread over a 256-thread block, fixed tree order.
+// Every thread returns the total. Uses 256 doubles of shared memory.
+__device__ inline double block_sum_256(double v, double *sh) {
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Sum of partials[0..n) in a fixed order (strided per-thread sums, then the
+// block tree). Identical in every block that calls it with the same input.
+__device__ inline double block_sum_array(const double *partials, int n, double *sh) {
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    double acc = 0.0;
+    for (int k = t; k < n; k += kBlock) acc += partials[k];
+    return block_sum_256(acc, sh);
+}
+
+__device__ inline bool skip_now(const int *skip) { return skip != nullptr && *skip != 0; }
+
+}  // namespace tnlm

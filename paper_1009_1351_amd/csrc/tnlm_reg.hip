@@ -1,0 +1,345 @@
+// TNLM regulariser: Eq. 8 patch weights over the §2.3 search window of the two
+// neighbouring phases, fused with one Gauss-Jacobi sweep of Eq. 7 and the
+// positivity clamp of the TNLM algorithm box:
+//   out_i(x) = g_i(x)/(1+mu) + mu/(2mu+2) * sum_{j = i-1, i+1} A_j(x),
+//   A_j(x)   = sum_y w_ij(x,y) value_j(y) / sum_y w_ij(x,y),
+//   w_ij     = exp(-(D(x,y) - min_y D)/h^2),  D = SSD of d x d guide patches,
+// with y over the W x W window truncated to the image and patch pixels outside
+// the image replaced by the nearest edge pixel.
+//
+// CDNA4 mapping (one 256-thread block per output tile of 32 rows x (32-2S)
+// columns of one phase; S = (d-1)/2, R = (W-1)/2):
+//   * guide/value tiles of both neighbour phases, with the window and patch
+//     halo, are staged once in LDS (edge-clamped at load time);
+//   * wave w handles neighbour j = w & 1 and half of the window rows
+//     (dy <= 0 or dy > 0); its 64 lanes are 4 rows of 16 lanes, each lane
+//     owns 2 adjacent columns and 8 output rows;
+//   * per offset (dx, dy) a lane forms the squared differences E of its
+//     columns over 8 + 2S rows against its own phase's values held in
+//     registers, sums them across columns with DPP row shifts (16-lane rows,
+//     (32-2S)/32 of the lanes produce valid columns), and down its rows in
+//     registers -- all sums are of non-negative terms, no sliding subtraction;
+//   * the weights are accumulated with a running minimum distance (online
+//     normalisation: a new minimum rescales the running sums), so each pair
+//     costs one exp2 and the result equals Eq. 8 with the window-minimum shift;
+//   * the two window halves and the two neighbours are merged through LDS;
+//     the epilogue applies Eq. 7, the clamp, and emits the partial sums of the
+//     relative update ||f_new - f_old||, ||f_new|| when asked.
+#include "devutil.h"
+#include "internal.h"
+
+namespace tnlm {
+
+struct RegArgs {
+    int N, L, R;
+    float nk;        // -log2(e) / h^2
+    float cs, cn;    // 1/(1+mu), mu/(2mu+2)
+    const float *guide, *value, *g;
+    float *out;
+    int clamp;
+    double *relpart;
+    int *nonfinite;
+    const int *skip;
+};
+
+constexpr int kBY = 8;   // output rows per lane
+
+// Value of x held by lane (l + K) of the same 16-lane row; 0 outside the row.
+template <int K>
+__device__ __forceinline__ float rowsh(float x) {
+    if constexpr (K == 0) {
+        return x;
+    } else if constexpr (K > 0) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x100 + K, 0xF,
+                                                                     0xF, true));   // row_shl:K
+    } else {
+        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x110 - K, 0xF,
+                                                                     0xF, true));   // row_shr:-K
+    }
+}
+
+template <int K0, int K1>
+__device__ __forceinline__ float rowsum(float x) {
+    if constexpr (K0 > K1) return 0.0f;
+    else if constexpr (K0 == K1) return rowsh<K0>(x);
+    else return rowsh<K0>(x) + rowsum<K0 + 1, K1>(x);
+}
+
+// Patch-row sums for the lane's two columns xa = base + 2l (value ea) and
+// xb = xa + 1 (value eb): ha = sum of E over columns xa-S..xa+S, hb over xb-S..xb+S.
+template <int S>
+__device__ __forceinline__ void hsum(float ea, float eb, float &ha, float &hb) {
+    const float p = ea + eb;
+    if constexpr (S % 2 == 1) {
+        constexpr int H = (S - 1) / 2;
+        const float qs = rowsum<-H, H>(p);
+        ha = qs + rowsh<-(S + 1) / 2>(eb);
+        hb = qs + rowsh<(S + 1) / 2>(ea);
+    } else {
+        constexpr int H = S / 2;
+        ha = rowsum<-H, H - 1>(p) + rowsh<H>(ea);
+        hb = rowsh<-H>(eb) + rowsum<-H + 1, H>(p);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ bool lane_valid_a(int l) {
+    if constexpr (S % 2 == 1) return l >= (S + 1) / 2 && l + (S - 1) / 2 <= 15;
+    else return l >= S / 2 && l + S / 2 <= 15;
+}
+template <int S>
+__device__ __forceinline__ bool lane_valid_b(int l) {
+    if constexpr (S % 2 == 1) return l >= (S - 1) / 2 && l + (S + 1) / 2 <= 15;
+    else return l >= S / 2 && l + S / 2 <= 15;
+}
+
+__device__ __forceinline__ void online_add(float D, float v, float nk, float &Dm, float &num, float &den) {
+    if (D < Dm) {   // new window minimum: rescale the running sums
+        const float sc = __builtin_amdgcn_exp2f((Dm - D) * nk);
+        num *= sc;
+        den *= sc;
+        Dm = D;
+    }
+    const float w = __builtin_amdgcn_exp2f((D - Dm) * nk);
+    num = fmaf(w, v, num);
+    den += w;
+}
+
+__device__ __forceinline__ void merge(float nk, float Dm1, float num1, float den1, float &Dm, float &num, float &den) {
+    const float m = fminf(Dm, Dm1);
+    const float s0 = __builtin_amdgcn_exp2f((Dm - m) * nk);
+    const float s1 = __builtin_amdgcn_exp2f((Dm1 - m) * nk);
+    num = num * s0 + num1 * s1;
+    den = den * s0 + den1 * s1;
+    Dm = m;
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
+    extern __shared__ float lds[];
+    __shared__ double shred[kBlock];
+    if (skip_now(a.skip)) return;
+    constexpr int TW = 32 - 2 * S, TH = 4 * kBY, NR = kBY + 2 * S;
+    const int R = a.R, L = a.L, N = a.N;
+    const int TCW = 32 + 2 * R, TRH = TH + 2 * S + 2 * R, TS = TCW * TRH;
+    const int i = blockIdx.z;
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    const int nbr0 = (i - 1 + N) % N, nbr1 = (i + 1) % N;
+    const bool same = a.value == a.guide;
+    const size_t plane = (size_t)L * L;
+
+    float *tg0 = lds, *tg1 = lds + TS;
+    float *tv0 = same ? tg0 : lds + 2 * TS, *tv1 = same ? tg1 : lds + 3 * TS;
+    const int col0 = x0 - S - R, row0 = y0 - S - R;
+    for (int e = threadIdx.x; e < TS; e += kBlock) {
+        const int tr = e / TCW, tc = e - tr * TCW;
+        const int gr = min(max(row0 + tr, 0), L - 1), gc = min(max(col0 + tc, 0), L - 1);
+        const size_t off = (size_t)gr * L + gc;
+        tg0[e] = a.guide[nbr0 * plane + off];
+        tg1[e] = a.guide[nbr1 * plane + off];
+        if (!same) {
+            tv0[e] = a.value[nbr0 * plane + off];
+            tv1[e] = a.value[nbr1 * plane + off];
+        }
+    }
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nsel = wave & 1, half = wave >> 1;
+    const int l16 = lane & 15, band = lane >> 4;
+    const int xa = x0 - S + 2 * l16;
+    const int zbase = y0 + band * kBY - S;
+
+    float gia[NR], gib[NR];
+    {
+        const float *gi = a.guide + (size_t)i * plane;
+        const int ca = min(max(xa, 0), L - 1), cb = min(max(xa + 1, 0), L - 1);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int zr = min(max(zbase + k, 0), L - 1);
+            gia[k] = gi[(size_t)zr * L + ca];
+            gib[k] = gi[(size_t)zr * L + cb];
+        }
+    }
+    const bool va = lane_valid_a<S>(l16) && xa >= x0 && xa < x0 + TW && xa < L;
+    const bool vb = lane_valid_b<S>(l16) && xa + 1 >= x0 && xa + 1 < x0 + TW && xa + 1 < L;
+
+    float Dma[kBY], numa[kBY], dena[kBY], Dmb[kBY], numb[kBY], denb[kBY];
+#pragma unroll
+    for (int o = 0; o < kBY; ++o) {
+        Dma[o] = Dmb[o] = INFINITY;
+        numa[o] = dena[o] = numb[o] = denb[o] = 0.0f;
+    }
+    __syncthreads();
+
+    const float *TG = nsel ? tg1 : tg0;
+    const float *TV = nsel ? tv1 : tv0;
+    const int dy0 = half == 0 ? -R : 1, dy1 = half == 0 ? 0 : R;
+    const int ta = 2 * l16 + R;
+    const int trb = band * kBY + R;
+    const float nk = a.nk;
+    const int yb = y0 + band * kBY;
+
+    for (int dy = dy0; dy <= dy1; ++dy) {
+        for (int dx = -R; dx <= R; ++dx) {
+            float ha[NR], hb[NR];
+            const float *rowp = TG + (trb + dy) * TCW + ta + dx;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                float ea = gia[k] - rowp[k * TCW];
+                float eb = gib[k] - rowp[k * TCW + 1];
+                ea *= ea;
+                eb *= eb;
+                hsum<S>(ea, eb, ha[k], hb[k]);
+            }
+            const bool ca = va && (unsigned)(xa + dx) < (unsigned)L;
+            const bool cb = vb && (unsigned)(xa + 1 + dx) < (unsigned)L;
+            const float *vp = TV + (band * kBY + S + R + dy) * TCW + ta + dx;
+            float p2a[NR - 1], p2b[NR - 1];
+#pragma unroll
+            for (int k = 0; k + 1 < NR; ++k) {
+                p2a[k] = ha[k] + ha[k + 1];
+                p2b[k] = hb[k] + hb[k + 1];
+            }
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                float Da = ha[o + 2 * S], Db = hb[o + 2 * S];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    Da += p2a[o + 2 * j];
+                    Db += p2b[o + 2 * j];
+                }
+                const bool rv = (unsigned)(yb + o + dy) < (unsigned)L;
+                if (rv && ca) online_add(Da, vp[o * TCW], nk, Dma[o], numa[o], dena[o]);
+                if (rv && cb) online_add(Db, vp[o * TCW + 1], nk, Dmb[o], numb[o], denb[o]);
+            }
+        }
+    }
+
+    // ---- merge the two window halves (waves 2,3 -> waves 0,1), then the two neighbours
+    __syncthreads();   // tiles no longer needed
+    float *mrg = lds;  // [2][64][2*kBY][3]
+    if (half == 1) {
+        float *p = mrg + ((size_t)(nsel * 64 + lane) * 2 * kBY) * 3;
+#pragma unroll
+        for (int o = 0; o < kBY; ++o) {
+            p[3 * o + 0] = Dma[o]; p[3 * o + 1] = numa[o]; p[3 * o + 2] = dena[o];
+            p[3 * (kBY + o) + 0] = Dmb[o]; p[3 * (kBY + o) + 1] = numb[o]; p[3 * (kBY + o) + 2] = denb[o];
+        }
+    }
+    __syncthreads();
+    float Aa[kBY], Ab[kBY];
+    if (half == 0) {
+        const float *p = mrg + ((size_t)(nsel * 64 + lane) * 2 * kBY) * 3;
+#pragma unroll
+        for (int o = 0; o < kBY; ++o) {
+            merge(nk, p[3 * o + 0], p[3 * o + 1], p[3 * o + 2], Dma[o], numa[o], dena[o]);
+            merge(nk, p[3 * (kBY + o) + 0], p[3 * (kBY + o) + 1], p[3 * (kBY + o) + 2], Dmb[o], numb[o], denb[o]);
+            Aa[o] = numa[o] / dena[o];
+            Ab[o] = numb[o] / denb[o];
+        }
+    }
+    __syncthreads();
+    float *ax = lds + 3 * 2 * 64 * 2 * kBY;   // [64][2*kBY]
+    if (wave == 1) {
+#pragma unroll
+        for (int o = 0; o < kBY; ++o) {
+            ax[lane * 2 * kBY + o] = Aa[o];
+            ax[lane * 2 * kBY + kBY + o] = Ab[o];
+        }
+    }
+    __syncthreads();
+    double dd = 0.0, nn = 0.0;
+    if (wave == 0) {
+        const float *gi = a.g + (size_t)i * plane;
+        float *oi = a.out + (size_t)i * plane;
+        bool bad = false;
+#pragma unroll
+        for (int o = 0; o < kBY; ++o) {
+            const int yo = yb + o;
+            if (yo >= L) continue;
+            if (va) {
+                const size_t e = (size_t)yo * L + xa;
+                float u = fmaf(a.cn, Aa[o] + ax[lane * 2 * kBY + o], a.cs * gi[e]);
+                if (a.clamp) u = fmaxf(u, 0.0f);
+                if (a.relpart) {
+                    const double df = (double)u - (double)oi[e];
+                    dd += df * df;
+                    nn += (double)u * (double)u;
+                }
+                bad |= !isfinite(u);
+                oi[e] = u;
+            }
+            if (vb) {
+                const size_t e = (size_t)yo * L + xa + 1;
+                float u = fmaf(a.cn, Ab[o] + ax[lane * 2 * kBY + kBY + o], a.cs * gi[e]);
+                if (a.clamp) u = fmaxf(u, 0.0f);
+                if (a.relpart) {
+                    const double df = (double)u - (double)oi[e];
+                    dd += df * df;
+                    nn += (double)u * (double)u;
+                }
+                bad |= !isfinite(u);
+                oi[e] = u;
+            }
+        }
+        if (bad && a.nonfinite) *a.nonfinite = 1;
+    }
+    if (a.relpart) {
+        dd = block_sum_256(dd, shred);
+        nn = block_sum_256(nn, shred);
+        if (threadIdx.x == 0) {
+            const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            a.relpart[2 * blk] = dd;
+            a.relpart[2 * blk + 1] = nn;
+        }
+    }
+}
+
+static int tile_w(int patch) { return 32 - 2 * (patch / 2); }
+
+int reg_blocks(const RegShape &s) {
+    const int tw = tile_w(s.patch), th = 4 * kBY;
+    return ((s.L + tw - 1) / tw) * ((s.L + th - 1) / th) * s.N;
+}
+
+bool reg_supported(int patch, int window) {
+    return patch >= 3 && patch <= 9 && (patch & 1) && window >= 3 && window <= 21 && (window & 1);
+}
+
+static size_t reg_lds_bytes(const RegShape &s, bool same) {
+    const int S = s.patch / 2, R = s.window / 2;
+    const size_t ts = (size_t)(32 + 2 * R) * (4 * kBY + 2 * S + 2 * R);
+    const size_t tiles = (same ? 2 : 4) * ts;
+    const size_t merge = 3 * 2 * 64 * 2 * kBY + 64 * 2 * kBY;
+    return std::max(tiles, merge) * sizeof(float);
+}
+
+void launch_regularize(const RegShape &s, const float *guide, const float *value, const float *g, float *out,
+                       int clamp, double *relpart, int *nonfinite, const int *skip, hipStream_t st) {
+    RegArgs a;
+    a.N = s.N;
+    a.L = s.L;
+    a.R = s.window / 2;
+    a.nk = (float)(-1.4426950408889634 / ((double)s.h * (double)s.h));
+    a.cs = (float)(1.0 / (1.0 + (double)s.mu_hat));
+    a.cn = (float)((double)s.mu_hat / (2.0 * (double)s.mu_hat + 2.0));
+    a.guide = guide;
+    a.value = value;
+    a.g = g;
+    a.out = out;
+    a.clamp = clamp;
+    a.relpart = relpart;
+    a.nonfinite = nonfinite;
+    a.skip = skip;
+    const int tw = tile_w(s.patch), th = 4 * kBY;
+    dim3 grid((s.L + tw - 1) / tw, (s.L + th - 1) / th, s.N);
+    const size_t lds = reg_lds_bytes(s, value == guide);
+    switch (s.patch / 2) {
+        case 1: k_tnlm_reg<1><<<grid, kBlock, lds, st>>>(a); break;
+        case 2: k_tnlm_reg<2><<<grid, kBlock, lds, st>>>(a); break;
+        case 3: k_tnlm_reg<3><<<grid, kBlock, lds, st>>>(a); break;
+        default: k_tnlm_reg<4><<<grid, kBlock, lds, st>>>(a); break;
+    }
+}
+
+}  // namespace tnlm
