@@ -172,6 +172,45 @@ tnlm_status tnlm_timing_enable(tnlm_ctx *ctx, int32_t enable);
 tnlm_status tnlm_timing_read(tnlm_ctx *ctx, double *ms /* [TNLM_KIND_COUNT] */,
                              int32_t *launches /* [TNLM_KIND_COUNT] */);
 
+/*
+ * Autotuner of the regulariser tile: times the two supported tile heights
+ * (4 or 8 output rows per lane, i.e. 16- or 32-row tiles) on the context's
+ * first slice with synthetic images, requires their outputs to agree
+ * bitwise, keeps the faster one for this context and appends the choice to a
+ * JSON-lines cache (env TNLM_AUTOTUNE_CACHE, default
+ * $HOME/.cache/tnlm_autotune.jsonl) keyed by (patch, window, L rounded up to
+ * a power of two); later contexts of that class start from the cached
+ * choice. rows_per_lane (nullable) receives the choice, ms (nullable, 2
+ * floats) the kernel times of the 8- and 4-row candidates. Synchronises.
+ */
+tnlm_status tnlm_autotune(tnlm_ctx *ctx, int32_t *rows_per_lane, float *ms);
+
+/*
+ * Batches of slices (many slices x N phases, uneven L, V, B). All slices
+ * share the parameters; each has its own geometry (geoms[n_slices], host,
+ * copied). One launch per stage covers every slice (blocks walk a ragged
+ * slice table persistently); one outer iteration of the whole batch is
+ * captured once into a hipGraph and replayed. Slices that reach
+ * tol_rel_update stop (their work items are skipped) while the others go on.
+ * The batch owns contiguous copies of y, w and f (inputs are copied in at
+ * the start of tnlm_batch_solve, results copied out at the end).
+ */
+typedef struct tnlm_batch tnlm_batch;
+tnlm_status tnlm_batch_init(tnlm_batch **out, int32_t n_slices, const tnlm_geometry *geoms,
+                            const tnlm_params *params, void *stream);
+void tnlm_batch_destroy(tnlm_batch *b);
+/*
+ * d_y, d_w, d_f: host arrays of n_slices device pointers (slice s: [N_s][V_s][B_s]
+ * and [N_s][L_s][L_s]). out_iters, out_rel (host [n_slices], nullable) and
+ * out_status (host [n_slices], nullable; per-slice TNLM_OK,
+ * TNLM_W_NOT_CONVERGED or TNLM_E_NONFINITE). Returns the worst status.
+ * Synchronises once at the end.
+ */
+tnlm_status tnlm_batch_solve(tnlm_batch *b, const float *const *d_y, const float *const *d_w, float *const *d_f,
+                             int32_t *out_iters, float *out_rel, tnlm_status *out_status);
+tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable);
+tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches);
+
 const char *tnlm_status_string(tnlm_status s);
 const char *tnlm_last_error(void);
 

@@ -6,11 +6,11 @@ the library's HIP kernels. Importing ``Recon`` requires the built library.
 """
 from __future__ import annotations
 
-__all__ = ["Recon", "TnlmError"]
+__all__ = ["Recon", "Batch", "TnlmError"]
 
 
 def __getattr__(name):
-    if name in ("Recon", "TnlmError"):
+    if name in ("Recon", "Batch", "TnlmError"):
         from . import recon
         return getattr(recon, name)
     raise AttributeError(name)

@@ -52,6 +52,13 @@ for _name, _args, _res in [
     ("tnlm_regularize", [_P, _P, _P, _P, _P, C.c_int32], C.c_int),
     ("tnlm_timing_enable", [_P, C.c_int32], C.c_int),
     ("tnlm_timing_read", [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
+    ("tnlm_autotune", [_P, C.POINTER(C.c_int32), _FP], C.c_int),
+    ("tnlm_batch_init", [C.POINTER(_P), C.c_int32, C.POINTER(Geometry), C.POINTER(Params), _P], C.c_int),
+    ("tnlm_batch_destroy", [_P], None),
+    ("tnlm_batch_solve", [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(C.c_int32), _FP,
+                          C.POINTER(C.c_int)], C.c_int),
+    ("tnlm_batch_timing_enable", [_P, C.c_int32], C.c_int),
+    ("tnlm_batch_timing_read", [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
     ("tnlm_status_string", [C.c_int], C.c_char_p),
     ("tnlm_last_error", [], C.c_char_p),
 ]:
@@ -63,7 +70,8 @@ for _name, _args, _res in [
 def exported_symbols():
     return ["tnlm_recon_init", "tnlm_destroy", "tnlm_step", "tnlm_solve", "tnlm_get_history", "tnlm_project",
             "tnlm_backproject", "tnlm_fbp", "tnlm_data_step", "tnlm_regularize", "tnlm_timing_enable",
-            "tnlm_timing_read", "tnlm_status_string", "tnlm_last_error"]
+            "tnlm_timing_read", "tnlm_autotune", "tnlm_batch_init", "tnlm_batch_destroy", "tnlm_batch_solve",
+            "tnlm_batch_timing_enable", "tnlm_batch_timing_read", "tnlm_status_string", "tnlm_last_error"]
 
 
 KIND_NAMES = ["project", "backproject", "regularize", "vector", "fbp", "other"]

@@ -1,13 +1,17 @@
 // Host side of the C ABI declared in include/tnlm.h: argument validation,
-// geometry tables, scratch ownership, and the enqueue order of one outer
-// iteration of the TNLM algorithm box (§2.2).
+// geometry tables, the ragged slice table, scratch ownership, and the enqueue
+// order of one outer iteration of the TNLM algorithm box (§2.2), optionally
+// captured once into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <memory>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -32,29 +36,52 @@ tnlm_status fail(tnlm_status s, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));                        \
     } while (0)
 
+constexpr int kCUs = 256;
+
 }  // namespace
 
-struct tnlm_ctx {
+enum {
+    K_PROJECT = TNLM_KIND_PROJECT,
+    K_BACKPROJECT = TNLM_KIND_BACKPROJECT,
+    K_REGULARIZE = TNLM_KIND_REGULARIZE,
+    K_VECTOR = TNLM_KIND_VECTOR,
+    K_FBP = TNLM_KIND_FBP,
+    K_OTHER = TNLM_KIND_OTHER
+};
+
+// Everything one batch of slices needs on the device; a single-slice context
+// is a batch of one.
+struct Engine {
     int device = 0;
     hipStream_t stream = nullptr;
-    tnlm_geometry geom{};
-    std::vector<double> angles;
+    hipStream_t capture_stream = nullptr;
     tnlm_params prm{};
-    DevGeom dg{};
-    RegShape rs{};
+    int ns = 0;
+    std::vector<tnlm_geometry> geoms;
+    std::vector<std::vector<double>> angles;
+    std::vector<SliceDesc> sl;
     std::vector<void *> allocs;
+    Batch batch{};
+    SliceDesc *d_sl = nullptr;
     float4 *rt0 = nullptr, *rt1 = nullptr, *vt = nullptr;
     float *hfilt = nullptr, *cw = nullptr;
+    Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{};
     CglsBufs cb{};
-    float *Q = nullptr;         // filtered sinogram / Eq. 4 scratch [N][V][B]
-    float *ua = nullptr, *ub = nullptr;   // Gauss-Jacobi ping-pong [N][L][L]
+    float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
-    int nrelblk = 0;
-    int *flags = nullptr;       // [0] zero, [1] done, [2] counter, [3] nonfinite
-    float *hist = nullptr;      // [max_outer]
+    int *flags = nullptr;   // [4][ns]: done, counter, nonfinite, spare
+    float *hist = nullptr;  // [ns][max_outer]
+    float *Y = nullptr, *Wt = nullptr, *F = nullptr;   // batch copies of caller arrays
     size_t nimg = 0, nsino = 0;
+    int rows_per_lane = 8;
+    RegParams rp{};
+    // graph of one outer iteration for a given (y, w, f)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *gkey[3] = {nullptr, nullptr, nullptr};
+    bool use_graph = true;
 
-    // kernel timing (HIP events around every launch on the context's stream)
+    // kernel timing (HIP events around every launch)
     struct TimedRec {
         int kind;
         hipEvent_t a, b;
@@ -63,6 +90,22 @@ struct tnlm_ctx {
     std::vector<TimedRec> recs;
     std::vector<hipEvent_t> pool;
     TimedRec pending{};
+    hipStream_t cur = nullptr;   // stream the enqueue functions target
+
+    int *done() { return flags; }
+    int *counter() { return flags + ns; }
+    int *nonfinite() { return flags + 2 * ns; }
+
+    template <class T>
+    hipError_t alloc(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) {
+            allocs.push_back(q);
+            *p = (T *)q;
+        }
+        return e;
+    }
     hipEvent_t take_event() {
         hipEvent_t e = nullptr;
         if (!pool.empty()) {
@@ -78,52 +121,73 @@ struct tnlm_ctx {
         pending.kind = kind;
         pending.a = take_event();
         pending.b = take_event();
-        (void)hipEventRecord(pending.a, stream);
+        (void)hipEventRecord(pending.a, cur);
     }
     void tend() {
         if (!timing) return;
-        (void)hipEventRecord(pending.b, stream);
+        (void)hipEventRecord(pending.b, cur);
         recs.push_back(pending);
     }
-
-    template <class T>
-    hipError_t alloc(T **p, size_t count) {
-        void *q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
-        if (e == hipSuccess) {
-            allocs.push_back(q);
-            *p = (T *)q;
-        }
-        return e;
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        gkey[0] = gkey[1] = gkey[2] = nullptr;
     }
-    ~tnlm_ctx() {
+    ~Engine() {
+        (void)hipStreamSynchronize(stream);
+        drop_graph();
         for (auto &r : recs) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
         }
         for (auto e : pool) (void)hipEventDestroy(e);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         for (void *p : allocs) (void)hipFree(p);
     }
-    int *zero() { return flags + 0; }
-    int *done() { return flags + 1; }
-    int *counter() { return flags + 2; }
-    int *nonfinite() { return flags + 3; }
 };
 
-static tnlm_status validate(const tnlm_geometry *g, const tnlm_params *p) {
-    if (!g || !p) return fail(TNLM_E_INVALID_ARG, "null geometry or params");
+struct tnlm_ctx {
+    Engine e;
+};
+struct tnlm_batch {
+    Engine e;
+};
+
+#define TIMED(E, kind, expr) \
+    do {                     \
+        (E)->tbegin(kind);   \
+        expr;                \
+        (E)->tend();         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// validation and tables
+// ---------------------------------------------------------------------------
+static tnlm_status validate_geom(const tnlm_geometry *g) {
+    if (!g) return fail(TNLM_E_INVALID_ARG, "null geometry");
     if (g->n_phases < 1 || g->L < 1 || g->L > 4096 || g->n_views < 1 || g->n_bins < 1 || g->n_bins > 4096)
         return fail(TNLM_E_SHAPE, "need N >= 1, 1 <= L <= 4096, V >= 1, 1 <= B <= 4096");
+    if ((long long)g->n_phases * g->n_views * g->n_bins > (1LL << 31) ||
+        (long long)g->n_phases * g->L * g->L > (1LL << 31))
+        return fail(TNLM_E_SHAPE, "slice too large");
     if (!(g->pixel_mm > 0) || !(g->sad_mm > 0) || !(g->dgamma_rad > 0) || !g->view_angles_rad)
         return fail(TNLM_E_INVALID_ARG, "need pixel_mm, sad_mm, dgamma_rad > 0 and view angles");
     if (!std::isfinite(g->det_offset_bins)) return fail(TNLM_E_INVALID_ARG, "det_offset_bins not finite");
     const double half_diag = 0.7071067811865476 * g->pixel_mm * g->L;
-    if (!(g->sad_mm > half_diag)) return fail(TNLM_E_INVALID_ARG, "source circle must enclose the image square");
+    if (!(g->sad_mm > half_diag + 2.0 * g->pixel_mm))
+        return fail(TNLM_E_INVALID_ARG, "the source circle must enclose the image square (SAD > half-diagonal + 2 pixels)");
     for (long k = 0; k < (long)g->n_phases * g->n_views; ++k)
         if (!std::isfinite(g->view_angles_rad[k])) return fail(TNLM_E_NONFINITE, "non-finite view angle");
+    return TNLM_OK;
+}
+
+static tnlm_status validate_params(const tnlm_params *p, int minL) {
+    if (!p) return fail(TNLM_E_INVALID_ARG, "null params");
     if (!(p->patch & 1) || !(p->window & 1) || !reg_supported(p->patch, p->window))
         return fail(TNLM_E_INVALID_ARG, "patch must be odd in [3,9], window odd in [3,21]");
-    if (p->window > g->L) return fail(TNLM_E_SHAPE, "window larger than the image");
+    if (p->window > minL) return fail(TNLM_E_SHAPE, "window larger than the image");
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(TNLM_E_INVALID_ARG, "h must be > 0");
     if (!(p->mu_hat >= 0) || !std::isfinite(p->mu_hat)) return fail(TNLM_E_INVALID_ARG, "mu_hat must be >= 0");
     if (!(p->beta > 0) || !std::isfinite(p->beta)) return fail(TNLM_E_INVALID_ARG, "beta must be > 0");
@@ -134,22 +198,21 @@ static tnlm_status validate(const tnlm_geometry *g, const tnlm_params *p) {
     if (p->init != TNLM_INIT_FBP_ALL && p->init != TNLM_INIT_USER) return fail(TNLM_E_INVALID_ARG, "bad init");
     if (p->ssd_mode != TNLM_SSD_FP32 && p->ssd_mode != TNLM_SSD_BF16_MFMA)
         return fail(TNLM_E_INVALID_ARG, "bad ssd_mode");
+    if (p->ssd_mode == TNLM_SSD_BF16_MFMA && !reg_mfma_supported(p->patch, p->window))
+        return fail(TNLM_E_INVALID_ARG, "ssd_mode BF16_MFMA supports patch 3, 5, 7 and window <= 15");
     return TNLM_OK;
 }
 
 // Per-ray plane tables in double precision, rounded once to float.
-static void build_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
-                         std::vector<float4> &vt, std::vector<float> &hf, std::vector<float> &cw) {
+static void append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
+                          std::vector<float4> &vt, std::vector<float> &hf, std::vector<float> &cw) {
     const int N = g.n_phases, V = g.n_views, B = g.n_bins, L = g.L;
     const double D = g.pixel_mm, X0 = -0.5 * D * L;
-    rt0.resize((size_t)N * V * B);
-    rt1.resize((size_t)N * V * B);
-    vt.resize((size_t)N * V);
     for (int i = 0; i < N; ++i)
         for (int v = 0; v < V; ++v) {
             const double th = g.view_angles_rad[(size_t)i * V + v];
             const double sx = g.sad_mm * std::cos(th), sy = g.sad_mm * std::sin(th);
-            vt[(size_t)i * V + v] = make_float4((float)sx, (float)sy, (float)std::cos(th), (float)std::sin(th));
+            vt.push_back(make_float4((float)sx, (float)sy, (float)std::cos(th), (float)std::sin(th)));
             for (int b = 0; b < B; ++b) {
                 const double gam = ((double)b - 0.5 * (B - 1) + g.det_offset_bins) * g.dgamma_rad;
                 const double ux = std::cos(th + M_PI + gam), uy = std::sin(th + M_PI + gam);
@@ -157,12 +220,11 @@ static void build_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::
                 const double ox = sx + ts * ux, oy = sy + ts * uy;
                 const double ix = std::fabs(ux) > 1e-9 ? 1.0 / ux : std::copysign(1e9, ux == 0 ? 1.0 : ux);
                 const double iy = std::fabs(uy) > 1e-9 ? 1.0 / uy : std::copysign(1e9, uy == 0 ? 1.0 : uy);
-                const size_t k = ((size_t)i * V + v) * B + b;
-                rt0[k] = make_float4((float)(D * ix), (float)((X0 - ox) * ix), (float)(D * iy), (float)((X0 - oy) * iy));
-                rt1[k] = make_float4((float)ox, (float)oy, (float)ux, (float)uy);
+                rt0.push_back(make_float4((float)(D * ix), (float)((X0 - ox) * ix), (float)(D * iy),
+                                          (float)((X0 - oy) * iy)));
+                rt1.push_back(make_float4((float)ox, (float)oy, (float)ux, (float)uy));
             }
         }
-    hf.resize(2 * (size_t)B - 1);
     const double a = g.dgamma_rad;
     for (int m = -(B - 1); m <= B - 1; ++m) {
         double h;
@@ -172,226 +234,501 @@ static void build_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::
             const double s = std::sin(m * a);
             h = -1.0 / (2.0 * M_PI * M_PI * s * s);
         }
-        hf[m + B - 1] = (float)(a * h);
+        hf.push_back((float)(a * h));
     }
-    cw.resize(B);
     for (int b = 0; b < B; ++b)
-        cw[b] = (float)(g.sad_mm * std::cos(((double)b - 0.5 * (B - 1) + g.det_offset_bins) * a));
+        cw.push_back((float)(g.sad_mm * std::cos(((double)b - 0.5 * (B - 1) + g.det_offset_bins) * a)));
 }
 
-extern "C" tnlm_status tnlm_recon_init(tnlm_ctx **out, const tnlm_geometry *geom, const tnlm_params *params,
-                                       void *stream) {
-    if (!out) return fail(TNLM_E_INVALID_ARG, "null output pointer");
-    *out = nullptr;
-    tnlm_status s = validate(geom, params);
-    if (s != TNLM_OK) return s;
-    if (params->ssd_mode == TNLM_SSD_BF16_MFMA)
-        return fail(TNLM_E_INVALID_ARG, "ssd_mode BF16_MFMA is not available in this build");
-    auto *c = new (std::nothrow) tnlm_ctx();
-    if (!c) return fail(TNLM_E_OOM, "host allocation failed");
-    std::unique_ptr<tnlm_ctx> guard(c);
-    HIP_TRY(hipGetDevice(&c->device));
-    c->stream = (hipStream_t)stream;
-    c->geom = *geom;
-    const int N = geom->n_phases, L = geom->L, V = geom->n_views, B = geom->n_bins;
-    c->angles.assign(geom->view_angles_rad, geom->view_angles_rad + (size_t)N * V);
-    c->geom.view_angles_rad = c->angles.data();
-    c->prm = *params;
-    c->nimg = (size_t)N * L * L;
-    c->nsino = (size_t)N * V * B;
-
-    std::vector<float4> rt0, rt1, vt;
-    std::vector<float> hf, cw;
-    build_tables(c->geom, rt0, rt1, vt, hf, cw);
-    HIP_TRY(c->alloc(&c->rt0, rt0.size()));
-    HIP_TRY(c->alloc(&c->rt1, rt1.size()));
-    HIP_TRY(c->alloc(&c->vt, vt.size()));
-    HIP_TRY(c->alloc(&c->hfilt, hf.size()));
-    HIP_TRY(c->alloc(&c->cw, cw.size()));
-    HIP_TRY(hipMemcpy(c->rt0, rt0.data(), rt0.size() * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->rt1, rt1.data(), rt1.size() * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->vt, vt.data(), vt.size() * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->hfilt, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->cw, cw.data(), cw.size() * sizeof(float), hipMemcpyHostToDevice));
-
-    DevGeom &d = c->dg;
-    d.N = N; d.L = L; d.V = V; d.B = B;
-    d.D = (float)geom->pixel_mm;
-    d.X0 = (float)(-0.5 * geom->pixel_mm * L);
-    d.dgamma = (float)geom->dgamma_rad;
-    d.ucenter = (float)(0.5 * (B - 1) - geom->det_offset_bins);
-    d.rt0 = c->rt0; d.rt1 = c->rt1; d.vt = c->vt;
-    c->rs = RegShape{N, L, params->patch, params->window, params->h, params->mu_hat};
-
-    CglsBufs &b = c->cb;
-    b.nbp = bp_blocks_per_phase(d);
-    b.npp = proj_blocks_per_phase(d);
-    HIP_TRY(c->alloc(&b.u, c->nimg));
-    HIP_TRY(c->alloc(&b.s, c->nimg));
-    HIP_TRY(c->alloc(&b.t, c->nimg));
-    HIP_TRY(c->alloc(&b.r, c->nsino));
-    HIP_TRY(c->alloc(&b.q, c->nsino));
-    HIP_TRY(c->alloc(&b.rw, c->nsino));
-    HIP_TRY(c->alloc(&b.sw, c->nsino));
-    HIP_TRY(c->alloc(&b.gpart[0], (size_t)N * b.nbp));
-    HIP_TRY(c->alloc(&b.gpart[1], (size_t)N * b.nbp));
-    HIP_TRY(c->alloc(&b.qpart, (size_t)N * b.npp));
-    HIP_TRY(c->alloc(&b.stop, (size_t)(params->m1_cgls + 2) * N));
-    HIP_TRY(c->alloc(&c->Q, c->nsino));
-    if (params->m2_jacobi > 1) {
-        HIP_TRY(c->alloc(&c->ua, c->nimg));
-        HIP_TRY(c->alloc(&c->ub, c->nimg));
-    }
-    c->nrelblk = reg_blocks(c->rs);
-    HIP_TRY(c->alloc(&c->relpart, 2 * (size_t)c->nrelblk));
-    HIP_TRY(c->alloc(&c->flags, 4));
-    HIP_TRY(c->alloc(&c->hist, (size_t)params->max_outer));
-    HIP_TRY(hipMemset(c->flags, 0, 4 * sizeof(int)));
-    HIP_TRY(hipDeviceSynchronize());
-    *out = guard.release();
+static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &counts, int cap) {
+    std::vector<int> pre(counts.size() + 1, 0);
+    for (size_t s = 0; s < counts.size(); ++s) pre[s + 1] = pre[s] + counts[s];
+    int *d = nullptr;
+    HIP_TRY(E.alloc(&d, pre.size()));
+    HIP_TRY(hipMemcpy(d, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
+    st.pre = d;
+    st.total = pre.back();
+    int g = std::min(st.total, cap);
+    if (g >= 8) g -= g % 8;
+    st.grid = std::max(1, g);
     return TNLM_OK;
 }
 
-extern "C" void tnlm_destroy(tnlm_ctx *ctx) {
-    if (!ctx) return;
-    (void)hipStreamSynchronize(ctx->stream);
-    delete ctx;
+static int autotuned_rows_per_lane(const tnlm_params &p, int L);
+
+static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, const tnlm_params *params,
+                               void *stream) {
+    if (ns < 1 || !geoms) return fail(TNLM_E_INVALID_ARG, "need at least one slice");
+    int minL = 1 << 30;
+    for (int s = 0; s < ns; ++s) {
+        tnlm_status st = validate_geom(&geoms[s]);
+        if (st != TNLM_OK) return st;
+        minL = std::min(minL, geoms[s].L);
+    }
+    tnlm_status st = validate_params(params, minL);
+    if (st != TNLM_OK) return st;
+    HIP_TRY(hipGetDevice(&E.device));
+    E.stream = (hipStream_t)stream;
+    E.cur = E.stream;
+    E.prm = *params;
+    E.ns = ns;
+    E.rp = RegParams{params->patch, params->window, params->h, params->mu_hat};
+    const char *env_rpl = std::getenv("TNLM_ROWS_PER_LANE");
+    E.rows_per_lane = env_rpl ? (std::atoi(env_rpl) == 4 ? 4 : 8) : autotuned_rows_per_lane(*params, geoms[0].L);
+    const char *env_graph = std::getenv("TNLM_NO_GRAPH");
+    E.use_graph = !(env_graph && env_graph[0] == '1');
+
+    std::vector<float4> rt0, rt1, vt;
+    std::vector<float> hf, cw;
+    E.geoms.assign(geoms, geoms + ns);
+    E.angles.resize(ns);
+    E.sl.resize(ns);
+    long long ray = 0, view = 0, img = 0, sino = 0;
+    int gp = 0, qp = 0, rpp = 0, phase = 0;
+    for (int s = 0; s < ns; ++s) {
+        const tnlm_geometry &g = geoms[s];
+        E.angles[s].assign(g.view_angles_rad, g.view_angles_rad + (size_t)g.n_phases * g.n_views);
+        E.geoms[s].view_angles_rad = E.angles[s].data();
+        SliceDesc &d = E.sl[s];
+        d.N = g.n_phases;
+        d.L = g.L;
+        d.V = g.n_views;
+        d.B = g.n_bins;
+        d.D = (float)g.pixel_mm;
+        d.X0 = (float)(-0.5 * g.pixel_mm * g.L);
+        d.dgamma = (float)g.dgamma_rad;
+        d.ucenter = (float)(0.5 * (g.n_bins - 1) - g.det_offset_bins);
+        d.ray0 = ray;
+        d.view0 = view;
+        d.img0 = img;
+        d.sino0 = sino;
+        d.hf0 = (int)hf.size();
+        d.cw0 = (int)cw.size();
+        append_tables(E.geoms[s], rt0, rt1, vt, hf, cw);
+        d.nbp = bp_blocks(d) / d.N;
+        d.npp = proj_blocks(d) / d.N;
+        d.nrb = params->ssd_mode == TNLM_SSD_BF16_MFMA ? reg_mfma_blocks(d)
+                                                       : reg_blocks(d, params->patch, E.rows_per_lane);
+        d.gp0 = gp;
+        d.qp0 = qp;
+        d.rp0 = rpp;
+        d.phase0 = phase;
+        gp += d.N * d.nbp;
+        qp += d.N * d.npp;
+        rpp += d.nrb;
+        phase += d.N;
+        ray += (long long)d.N * d.V * d.B;
+        view += (long long)d.N * d.V;
+        img += (long long)d.N * d.L * d.L;
+        sino += (long long)d.N * d.V * d.B;
+    }
+    E.nimg = (size_t)img;
+    E.nsino = (size_t)sino;
+    HIP_TRY(E.alloc(&E.d_sl, ns));
+    HIP_TRY(hipMemcpy(E.d_sl, E.sl.data(), ns * sizeof(SliceDesc), hipMemcpyHostToDevice));
+    HIP_TRY(E.alloc(&E.rt0, rt0.size()));
+    HIP_TRY(E.alloc(&E.rt1, rt1.size()));
+    HIP_TRY(E.alloc(&E.vt, vt.size()));
+    HIP_TRY(E.alloc(&E.hfilt, hf.size()));
+    HIP_TRY(E.alloc(&E.cw, cw.size()));
+    HIP_TRY(hipMemcpy(E.rt0, rt0.data(), rt0.size() * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(E.rt1, rt1.data(), rt1.size() * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(E.vt, vt.data(), vt.size() * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(E.hfilt, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(E.cw, cw.data(), cw.size() * sizeof(float), hipMemcpyHostToDevice));
+    E.batch.ns = ns;
+    E.batch.sl = E.d_sl;
+    E.batch.rt0 = E.rt0;
+    E.batch.rt1 = E.rt1;
+    E.batch.vt = E.vt;
+    E.batch.skip = nullptr;
+
+    std::vector<int> cfp, cbp, cvec, creg, cff, cfa, cfph;
+    for (auto &d : E.sl) {
+        cfp.push_back(proj_blocks(d));
+        cbp.push_back(bp_blocks(d));
+        cvec.push_back(d.N * vec_blocks(d));
+        creg.push_back(d.nrb);
+        cff.push_back(d.N * d.V);
+        cfa.push_back(fbp_bp_blocks(d, 1));
+        cfph.push_back(fbp_bp_blocks(d, 0));
+    }
+    if ((st = make_stage(E, E.st_fp, cfp, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_vec, cvec, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_reg, creg, kCUs * 4)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_ffilt, cff, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_fbp_all, cfa, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_fbp_ph, cfph, kCUs * 8)) != TNLM_OK) return st;
+
+    CglsBufs &b = E.cb;
+    HIP_TRY(E.alloc(&b.u, E.nimg));
+    HIP_TRY(E.alloc(&b.s, E.nimg));
+    HIP_TRY(E.alloc(&b.t, E.nimg));
+    HIP_TRY(E.alloc(&b.r, E.nsino));
+    HIP_TRY(E.alloc(&b.q, E.nsino));
+    HIP_TRY(E.alloc(&b.rw, E.nsino));
+    HIP_TRY(E.alloc(&b.sw, E.nsino));
+    HIP_TRY(E.alloc(&b.gpart[0], (size_t)gp));
+    HIP_TRY(E.alloc(&b.gpart[1], (size_t)gp));
+    HIP_TRY(E.alloc(&b.qpart, (size_t)qp));
+    b.nphase = phase;
+    HIP_TRY(E.alloc(&b.stop, (size_t)(params->m1_cgls + 2) * phase));
+    HIP_TRY(E.alloc(&E.Q, E.nsino));
+    if (params->m2_jacobi > 1) {
+        HIP_TRY(E.alloc(&E.ua, E.nimg));
+        HIP_TRY(E.alloc(&E.ub, E.nimg));
+    }
+    HIP_TRY(E.alloc(&E.relpart, 2 * (size_t)rpp));
+    HIP_TRY(E.alloc(&E.flags, 4 * (size_t)ns));
+    HIP_TRY(E.alloc(&E.hist, (size_t)ns * params->max_outer));
+    HIP_TRY(hipMemset(E.flags, 0, 4 * ns * sizeof(int)));
+    HIP_TRY(hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipDeviceSynchronize());
+    return TNLM_OK;
 }
 
-enum {
-    K_PROJECT = TNLM_KIND_PROJECT,
-    K_BACKPROJECT = TNLM_KIND_BACKPROJECT,
-    K_REGULARIZE = TNLM_KIND_REGULARIZE,
-    K_VECTOR = TNLM_KIND_VECTOR,
-    K_FBP = TNLM_KIND_FBP,
-    K_OTHER = TNLM_KIND_OTHER
-};
-
-#define TIMED(c, kind, expr) \
-    do {                         \
-        (c)->tbegin(kind);       \
-        expr;                    \
-        (c)->tend();             \
-    } while (0)
-
-// ---- data step: u <- CGLS_M1(f) (or Eq. 4), reading y, sw (= sqrt w) / w
-static void enqueue_data_step(tnlm_ctx *c, const float *y, const float *w, const float *f, const int *skip) {
-    const DevGeom &g = c->dg;
-    CglsBufs &b = c->cb;
-    hipStream_t st = c->stream;
-    const int M1 = c->prm.m1_cgls;
+// ---------------------------------------------------------------------------
+// enqueue order of one outer iteration
+// ---------------------------------------------------------------------------
+// data step: u <- CGLS_M1(f) (or Eq. 4), reading y, sw = sqrt(w) / w
+static void enqueue_data_step(Engine *E, const Batch &bt, const float *y, const float *w, const float *f) {
+    CglsBufs &b = E->cb;
+    hipStream_t st = E->cur;
+    const int M1 = E->prm.m1_cgls;
     if (M1 == 0) {
-        TIMED(c, K_PROJECT, launch_project(g, PROJ_PLAIN, f, nullptr, nullptr, b.q, nullptr, nullptr, skip, st));
-        TIMED(c, K_VECTOR, launch_weighted_resid(g, b.q, y, w, c->Q, skip, st));
-        TIMED(c, K_BACKPROJECT, launch_backproject(g, c->Q, b.t, nullptr, skip, st));
-        TIMED(c, K_VECTOR, launch_gradient_step(g, f, b.t, 1.0f / c->prm.beta, b.u, skip, st));
+        TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_PLAIN, f, nullptr, nullptr, b.q, nullptr, nullptr, st));
+        TIMED(E, K_VECTOR, launch_weighted_resid(bt, E->st_vec, b.q, y, w, E->Q, st));
+        TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, E->Q, b.t, nullptr, st));
+        TIMED(E, K_VECTOR, launch_gradient_step(bt, E->st_vec, f, b.t, 1.0f / E->prm.beta, b.u, st));
         return;
     }
-    TIMED(c, K_VECTOR, launch_copy(f, b.u, c->nimg, skip, st));
-    TIMED(c, K_PROJECT, launch_project(g, PROJ_RESID, b.u, y, b.sw, b.r, b.rw, nullptr, skip, st));  // r0, sw r0
-    TIMED(c, K_BACKPROJECT, launch_backproject(g, b.rw, b.s, b.gpart[0], skip, st));  // s0, ||s0||^2
+    TIMED(E, K_VECTOR, launch_copy_skip(bt, E->st_vec, true, f, b.u, st));
+    TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_RESID, b.u, y, b.sw, b.r, b.rw, nullptr, st));
+    TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.s, b.gpart[0], st));
     for (int m = 0; m < M1; ++m) {
-        TIMED(c, K_PROJECT, launch_project(g, PROJ_SCALED, b.s, nullptr, b.sw, b.q, nullptr, b.qpart, skip, st));
-        TIMED(c, K_VECTOR, launch_cgls_update(g, b, m, m & 1, skip, st));
+        TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_SCALED, b.s, nullptr, b.sw, b.q, nullptr, b.qpart, st));
+        TIMED(E, K_VECTOR, launch_cgls_update(bt, E->st_vec, b, m, m & 1, st));
         if (m + 1 < M1) {
-            TIMED(c, K_BACKPROJECT, launch_backproject(g, b.rw, b.t, b.gpart[(m + 1) & 1], skip, st));
-            TIMED(c, K_VECTOR, launch_cgls_direction(g, b, m, m & 1, (m + 1) & 1, skip, st));
+            TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.t, b.gpart[(m + 1) & 1], st));
+            TIMED(E, K_VECTOR, launch_cgls_direction(bt, E->st_vec, b, m, m & 1, (m + 1) & 1, st));
         }
     }
 }
 
-// ---- Gauss-Jacobi sweeps from g = u, weights from u; last sweep writes f (clamped)
-static void enqueue_regularize(tnlm_ctx *c, float *f, const int *skip, bool record) {
-    const float *g = c->cb.u;
-    const int M2 = c->prm.m2_jacobi;
+// Gauss-Jacobi sweeps from g = u, weights from u; last sweep writes f (clamped)
+static void enqueue_regularize(Engine *E, const Batch &bt, float *f, bool record) {
+    const float *g = E->cb.u;
+    const int M2 = E->prm.m2_jacobi;
     const float *val = g;
     for (int m = 0; m < M2; ++m) {
         const bool last = m + 1 == M2;
-        float *dst = last ? f : ((m & 1) ? c->ub : c->ua);
-        TIMED(c, K_REGULARIZE, launch_regularize(c->rs, g, val, g, dst, last ? 1 : 0, last && record ? c->relpart : nullptr,
-                          c->nonfinite(), skip, c->stream));
+        float *dst = last ? f : ((m & 1) ? E->ub : E->ua);
+        if (E->prm.ssd_mode == TNLM_SSD_BF16_MFMA)
+            TIMED(E, K_REGULARIZE,
+                  launch_regularize_mfma(bt, E->st_reg, E->rp, g, val, g, dst, last ? 1 : 0,
+                                         last && record ? E->relpart : nullptr, E->nonfinite(), E->cur));
+        else
+            TIMED(E, K_REGULARIZE,
+                  launch_regularize(bt, E->st_reg, E->rp, E->rows_per_lane, g, val, g, dst, last ? 1 : 0,
+                                    last && record ? E->relpart : nullptr, E->nonfinite(), E->cur));
         val = dst;
     }
 }
 
-static void enqueue_step(tnlm_ctx *c, const float *y, const float *w, float *f, const int *skip) {
-    enqueue_data_step(c, y, w, f, skip);
-    enqueue_regularize(c, f, skip, true);
-    TIMED(c, K_OTHER, launch_finalize(c->relpart, c->nrelblk, c->prm.tol_rel_update, c->hist, c->counter(), c->done(),
-                    c->nonfinite(), c->prm.max_outer, skip, c->stream));
+static void enqueue_step(Engine *E, const Batch &bt, const float *y, const float *w, float *f) {
+    enqueue_data_step(E, bt, y, w, f);
+    enqueue_regularize(E, bt, f, true);
+    TIMED(E, K_OTHER, launch_finalize(bt, E->relpart, E->prm.tol_rel_update, E->hist, E->counter(), E->done(),
+                                      E->nonfinite(), E->prm.max_outer, E->cur));
 }
 
+static tnlm_status last_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TNLM_E_HIP, hipGetErrorString(e));
+    return TNLM_OK;
+}
+
+// Graph of one outer iteration with the solve's skip flags, for (y, w, f).
+static bool ensure_graph(Engine *E, const Batch &bt, const float *y, const float *w, float *f) {
+    if (!E->use_graph || E->timing) return false;
+    if (E->gexec && E->gkey[0] == y && E->gkey[1] == w && E->gkey[2] == f) return true;
+    E->drop_graph();
+    if (hipStreamBeginCapture(E->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    E->cur = E->capture_stream;
+    enqueue_step(E, bt, y, w, f);
+    E->cur = E->stream;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(E->capture_stream, &g) != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        return false;
+    }
+    E->graph = g;
+    E->gexec = ex;
+    E->gkey[0] = y;
+    E->gkey[1] = w;
+    E->gkey[2] = f;
+    return true;
+}
+
+// Full solve on contiguous batch arrays (y, w, f); f holds f^(0) when init is user.
+static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float *f) {
+    hipStream_t st = E->stream;
+    E->cur = st;
+    const int ns = E->ns;
+    Batch bt = E->batch;
+    launch_fill_int(E->flags, 4 * ns, 0, st);
+    TIMED(E, K_OTHER, launch_check_finite(y, E->nsino, E->nonfinite(), st));
+    TIMED(E, K_OTHER, launch_check_finite(w, E->nsino, E->nonfinite(), st));
+    if (E->prm.init == TNLM_INIT_FBP_ALL)
+        TIMED(E, K_FBP, launch_fbp(bt, E->st_ffilt, E->st_fbp_all, y, E->hfilt, E->cw, E->Q, f, 1, st));
+    else
+        TIMED(E, K_OTHER, launch_check_finite(f, E->nimg, E->nonfinite(), st));
+    if (E->prm.m1_cgls > 0) TIMED(E, K_VECTOR, launch_sqrt(w, E->cb.sw, E->nsino, st));
+    std::vector<int> hf(4 * ns, 0);
+    HIP_TRY(hipMemcpyAsync(hf.data(), E->flags, hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int s = 0; s < ns; ++s)
+        if (hf[2 * ns + s])
+            return fail(TNLM_E_NONFINITE, "non-finite value in y, w or the initial image of slice " + std::to_string(s));
+    // converged (or failed) slices drop out: every iteration kernel skips them
+    bt.skip = E->done();
+    const bool graph = ensure_graph(E, bt, y, w, f);
+    const int K = E->prm.max_outer;
+    const bool early = E->prm.tol_rel_update > 0.0f;
+    const int chunk = 8;
+    for (int k = 0; k < K; ++k) {
+        if (graph) HIP_TRY(hipGraphLaunch(E->gexec, st));
+        else enqueue_step(E, bt, y, w, f);
+        if (early && ((k + 1) % chunk == 0) && k + 1 < K) {
+            HIP_TRY(hipMemcpyAsync(hf.data(), E->flags, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bool all = true;
+            for (int s = 0; s < ns; ++s) all = all && hf[s];
+            if (all) break;
+        }
+    }
+    tnlm_status ls = last_launch();
+    if (ls != TNLM_OK) return ls;
+    HIP_TRY(hipStreamSynchronize(st));
+    return TNLM_OK;
+}
+
+// per-slice results after engine_solve
+static tnlm_status engine_results(Engine *E, int32_t *iters, float *rel, tnlm_status *status) {
+    const int ns = E->ns;
+    std::vector<int> hf(4 * ns, 0);
+    HIP_TRY(hipMemcpy(hf.data(), E->flags, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
+    tnlm_status worst = TNLM_OK;
+    for (int s = 0; s < ns; ++s) {
+        const int it = std::min(hf[ns + s], E->prm.max_outer);
+        float r = 0.0f;
+        if (it > 0)
+            HIP_TRY(hipMemcpy(&r, E->hist + (size_t)s * E->prm.max_outer + (it - 1), sizeof(float),
+                              hipMemcpyDeviceToHost));
+        tnlm_status ss = TNLM_OK;
+        if (hf[2 * ns + s]) ss = TNLM_E_NONFINITE;
+        else if (E->prm.tol_rel_update > 0.0f && !(r < E->prm.tol_rel_update)) ss = TNLM_W_NOT_CONVERGED;
+        if (iters) iters[s] = it;
+        if (rel) rel[s] = r;
+        if (status) status[s] = ss;
+        if (ss < 0) worst = ss;
+        else if (ss > 0 && worst == TNLM_OK) worst = ss;
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: rows per lane of the regulariser tile (4 or 8), per (patch,
+// window, L class); both candidates are timed on the device and must agree
+// bitwise; results are cached as JSON lines (last entry of a key wins).
+// ---------------------------------------------------------------------------
+static std::string tune_cache_path() {
+    const char *p = std::getenv("TNLM_AUTOTUNE_CACHE");
+    if (p && *p) return p;
+    const char *home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/tnlm_autotune.jsonl";
+}
+
+static std::string tune_key(const tnlm_params &p, int L) {
+    int Lc = 64;
+    while (Lc < L) Lc *= 2;
+    std::ostringstream k;
+    k << "gfx950/patch" << p.patch << "/window" << p.window << "/L" << Lc;
+    return k.str();
+}
+
+static int autotuned_rows_per_lane(const tnlm_params &p, int L) {
+    std::ifstream in(tune_cache_path());
+    std::string line, key = "\"" + tune_key(p, L) + "\"";
+    int v = 8;
+    while (std::getline(in, line)) {
+        if (line.find(key) == std::string::npos) continue;
+        const size_t k = line.find("\"rows_per_lane\":");
+        if (k != std::string::npos) v = std::atoi(line.c_str() + k + 16) == 4 ? 4 : 8;
+    }
+    return v;
+}
+
+static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
+    if (E->prm.ssd_mode != TNLM_SSD_FP32) return fail(TNLM_E_INVALID_ARG, "the autotuner tunes the FP32 regulariser");
+    const SliceDesc &d0 = E->sl[0];
+    hipStream_t st = E->stream;
+    // synthetic test images on the first slice's layout
+    std::vector<float> h((size_t)d0.N * d0.L * d0.L);
+    unsigned x = 12345u;
+    for (size_t k = 0; k < h.size(); ++k) {
+        x = x * 1664525u + 1013904223u;
+        h[k] = 0.01f + 0.01f * (float)((x >> 8) & 0xffff) / 65536.0f;
+    }
+    float *g = nullptr, *o4 = nullptr, *o8 = nullptr;
+    SliceDesc *dd = nullptr;
+    int *pre = nullptr;
+    HIP_TRY(hipMalloc(&g, h.size() * sizeof(float)));
+    HIP_TRY(hipMalloc(&o4, h.size() * sizeof(float)));
+    HIP_TRY(hipMalloc(&o8, h.size() * sizeof(float)));
+    HIP_TRY(hipMalloc(&dd, 2 * sizeof(SliceDesc)));
+    HIP_TRY(hipMalloc(&pre, 4 * sizeof(int)));
+    HIP_TRY(hipMemcpy(g, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    float ms[2] = {0, 0};
+    const int cand[2] = {8, 4};
+    std::vector<float> out[2];
+    for (int c = 0; c < 2; ++c) {
+        SliceDesc d = d0;
+        d.img0 = 0;
+        d.rp0 = 0;
+        d.nrb = reg_blocks(d, E->prm.patch, cand[c]);
+        const int hp[2] = {0, d.nrb};
+        HIP_TRY(hipMemcpy(dd + c, &d, sizeof(SliceDesc), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(pre + 2 * c, hp, sizeof(hp), hipMemcpyHostToDevice));
+        Batch bt = E->batch;
+        bt.ns = 1;
+        bt.sl = dd + c;
+        bt.skip = nullptr;
+        Stage sg{pre + 2 * c, d.nrb, std::max(1, std::min(d.nrb, kCUs * 4))};
+        if (sg.grid >= 8) sg.grid -= sg.grid % 8;
+        float *o = c == 0 ? o8 : o4;
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        launch_regularize(bt, sg, E->rp, cand[c], g, g, g, o, 1, nullptr, nullptr, st);   // warm-up
+        HIP_TRY(hipEventRecord(a, st));
+        for (int r = 0; r < 5; ++r) launch_regularize(bt, sg, E->rp, cand[c], g, g, g, o, 1, nullptr, nullptr, st);
+        HIP_TRY(hipEventRecord(b, st));
+        HIP_TRY(hipEventSynchronize(b));
+        HIP_TRY(hipEventElapsedTime(&ms[c], a, b));
+        ms[c] /= 5.0f;
+        out[c].resize(h.size());
+        HIP_TRY(hipMemcpy(out[c].data(), o, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    (void)hipFree(g);
+    (void)hipFree(o4);
+    (void)hipFree(o8);
+    (void)hipFree(dd);
+    (void)hipFree(pre);
+    const bool same = std::memcmp(out[0].data(), out[1].data(), out[0].size() * sizeof(float)) == 0;
+    const int pick = (same && ms[1] < ms[0]) ? 4 : 8;
+    if (chosen) *chosen = pick;
+    if (ms_out) {
+        ms_out[0] = ms[0];
+        ms_out[1] = ms[1];
+    }
+    const std::string path = tune_cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        std::string cmd = "mkdir -p '" + dir + "'";
+        if (std::system(cmd.c_str()) != 0) { /* cache is best effort */ }
+    }
+    std::ofstream fo(path, std::ios::app);
+    if (fo)
+        fo << "{\"key\": \"" << tune_key(E->prm, d0.L) << "\", \"rows_per_lane\": " << pick << ", \"ms8\": " << ms[0]
+           << ", \"ms4\": " << ms[1] << ", \"bitwise_equal\": " << (same ? "true" : "false") << "}\n";
+    if (!same) return fail(TNLM_E_HIP, "autotune candidates disagree bitwise; kept the reference tile");
+    if (pick == E->rows_per_lane) return TNLM_OK;
+    E->rows_per_lane = pick;
+    // the regulariser's per-slice block counts depend on the tile height
+    int rpp = 0;
+    std::vector<int> creg;
+    for (auto &d : E->sl) {
+        d.nrb = reg_blocks(d, E->prm.patch, pick);
+        d.rp0 = rpp;
+        rpp += d.nrb;
+        creg.push_back(d.nrb);
+    }
+    HIP_TRY(hipMemcpy(E->d_sl, E->sl.data(), E->sl.size() * sizeof(SliceDesc), hipMemcpyHostToDevice));
+    HIP_TRY(E->alloc(&E->relpart, 2 * (size_t)rpp));
+    tnlm_status s2 = make_stage(*E, E->st_reg, creg, kCUs * 4);
+    E->drop_graph();
+    return s2;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
 #define CHECK_CTX()                                                                    \
     do {                                                                               \
         if (!ctx) return fail(TNLM_E_INVALID_ARG, "null context");                     \
     } while (0)
 
-#define CHECK_LAUNCH()                                                                 \
-    do {                                                                               \
-        hipError_t e_ = hipGetLastError();                                             \
-        if (e_ != hipSuccess) return fail(TNLM_E_HIP, hipGetErrorString(e_));          \
-    } while (0)
+extern "C" tnlm_status tnlm_recon_init(tnlm_ctx **out, const tnlm_geometry *geom, const tnlm_params *params,
+                                       void *stream) {
+    if (!out) return fail(TNLM_E_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!geom) return fail(TNLM_E_INVALID_ARG, "null geometry");
+    std::unique_ptr<tnlm_ctx> c(new (std::nothrow) tnlm_ctx());
+    if (!c) return fail(TNLM_E_OOM, "host allocation failed");
+    tnlm_status s = engine_init(c->e, 1, geom, params, stream);
+    if (s != TNLM_OK) return s;
+    *out = c.release();
+    return TNLM_OK;
+}
+
+extern "C" void tnlm_destroy(tnlm_ctx *ctx) { delete ctx; }
 
 extern "C" tnlm_status tnlm_step(tnlm_ctx *ctx, const float *d_y, const float *d_w, float *d_f) {
     CHECK_CTX();
     if (!d_y || !d_w || !d_f) return fail(TNLM_E_INVALID_ARG, "null device pointer");
-    if (ctx->prm.m1_cgls > 0) TIMED(ctx, K_VECTOR, launch_sqrt(d_w, ctx->cb.sw, ctx->nsino, ctx->stream));
-    enqueue_step(ctx, d_y, d_w, d_f, ctx->zero());
-    CHECK_LAUNCH();
-    return TNLM_OK;
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    if (E->prm.m1_cgls > 0) TIMED(E, K_VECTOR, launch_sqrt(d_w, E->cb.sw, E->nsino, E->stream));
+    enqueue_step(E, E->batch, d_y, d_w, d_f);
+    return last_launch();
 }
 
 extern "C" tnlm_status tnlm_solve(tnlm_ctx *ctx, const float *d_y, const float *d_w, float *d_f, int32_t *out_iters,
                                   float *out_rel) {
     CHECK_CTX();
     if (!d_y || !d_w || !d_f) return fail(TNLM_E_INVALID_ARG, "null device pointer");
-    hipStream_t st = ctx->stream;
-    HIP_TRY(hipMemsetAsync(ctx->flags, 0, 4 * sizeof(int), st));
-    TIMED(ctx, K_OTHER, launch_check_finite(d_y, ctx->nsino, ctx->nonfinite(), st));
-    TIMED(ctx, K_OTHER, launch_check_finite(d_w, ctx->nsino, ctx->nonfinite(), st));
-    if (ctx->prm.init == TNLM_INIT_FBP_ALL)
-        TIMED(ctx, K_FBP, launch_fbp(ctx->dg, d_y, ctx->hfilt, ctx->cw, ctx->Q, d_f, 1, (float)ctx->geom.sad_mm, st));
-    else
-        TIMED(ctx, K_OTHER, launch_check_finite(d_f, ctx->nimg, ctx->nonfinite(), st));
-    int host_flags[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(host_flags, ctx->flags, sizeof(host_flags), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (host_flags[3]) return fail(TNLM_E_NONFINITE, "non-finite value in y, w or the initial image");
-    if (ctx->prm.m1_cgls > 0) TIMED(ctx, K_VECTOR, launch_sqrt(d_w, ctx->cb.sw, ctx->nsino, st));
-    const int K = ctx->prm.max_outer;
-    const bool early = ctx->prm.tol_rel_update > 0.0f;
-    const int chunk = 8;
-    for (int k = 0; k < K; ++k) {
-        enqueue_step(ctx, d_y, d_w, d_f, ctx->done());
-        if (early && ((k + 1) % chunk == 0) && k + 1 < K) {
-            HIP_TRY(hipMemcpyAsync(host_flags, ctx->flags, sizeof(host_flags), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (host_flags[1]) break;
-        }
-    }
-    CHECK_LAUNCH();
-    HIP_TRY(hipMemcpyAsync(host_flags, ctx->flags, sizeof(host_flags), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const int iters = host_flags[2];
-    float rel = 0.0f;
-    if (iters > 0) HIP_TRY(hipMemcpy(&rel, ctx->hist + (iters - 1), sizeof(float), hipMemcpyDeviceToHost));
-    if (out_iters) *out_iters = iters;
-    if (out_rel) *out_rel = rel;
-    if (host_flags[3]) return fail(TNLM_E_NONFINITE, "an iterate became non-finite");
-    if (early && !(rel < ctx->prm.tol_rel_update)) {
-        g_last_error = "max_outer reached before tol_rel_update";
-        return TNLM_W_NOT_CONVERGED;
-    }
-    return TNLM_OK;
+    tnlm_status s = engine_solve(&ctx->e, d_y, d_w, d_f);
+    if (s != TNLM_OK) return s;
+    tnlm_status ss = TNLM_OK;
+    s = engine_results(&ctx->e, out_iters, out_rel, &ss);
+    if (s == TNLM_E_NONFINITE) return fail(s, "an iterate became non-finite");
+    if (s < 0) return s;
+    if (s == TNLM_W_NOT_CONVERGED) g_last_error = "max_outer reached before tol_rel_update";
+    return s;
 }
 
 extern "C" tnlm_status tnlm_get_history(tnlm_ctx *ctx, float *out, int32_t n, int32_t *out_n) {
     CHECK_CTX();
+    Engine *E = &ctx->e;
     int cnt = 0;
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    HIP_TRY(hipMemcpy(&cnt, ctx->counter(), sizeof(int), hipMemcpyDeviceToHost));
-    cnt = std::min(cnt, ctx->prm.max_outer);
-    if (out && n > 0) HIP_TRY(hipMemcpy(out, ctx->hist, sizeof(float) * std::min(n, cnt), hipMemcpyDeviceToHost));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    HIP_TRY(hipMemcpy(&cnt, E->counter(), sizeof(int), hipMemcpyDeviceToHost));
+    cnt = std::min(cnt, E->prm.max_outer);
+    if (out && n > 0) HIP_TRY(hipMemcpy(out, E->hist, sizeof(float) * std::min(n, cnt), hipMemcpyDeviceToHost));
     if (out_n) *out_n = cnt;
     return TNLM_OK;
 }
@@ -399,37 +736,44 @@ extern "C" tnlm_status tnlm_get_history(tnlm_ctx *ctx, float *out, int32_t n, in
 extern "C" tnlm_status tnlm_project(tnlm_ctx *ctx, const float *d_f, float *d_q) {
     CHECK_CTX();
     if (!d_f || !d_q) return fail(TNLM_E_INVALID_ARG, "null device pointer");
-    TIMED(ctx, K_PROJECT, launch_project(ctx->dg, PROJ_PLAIN, d_f, nullptr, nullptr, d_q, nullptr, nullptr, nullptr, ctx->stream));
-    CHECK_LAUNCH();
-    return TNLM_OK;
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    TIMED(E, K_PROJECT,
+          launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, nullptr, nullptr, d_q, nullptr, nullptr, E->stream));
+    return last_launch();
 }
 
 extern "C" tnlm_status tnlm_backproject(tnlm_ctx *ctx, const float *d_q, float *d_f) {
     CHECK_CTX();
     if (!d_f || !d_q) return fail(TNLM_E_INVALID_ARG, "null device pointer");
-    TIMED(ctx, K_BACKPROJECT, launch_backproject(ctx->dg, d_q, d_f, nullptr, nullptr, ctx->stream));
-    CHECK_LAUNCH();
-    return TNLM_OK;
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    TIMED(E, K_BACKPROJECT, launch_backproject(E->batch, E->st_bp, d_q, d_f, nullptr, E->stream));
+    return last_launch();
 }
 
 extern "C" tnlm_status tnlm_fbp(tnlm_ctx *ctx, const float *d_y, float *d_f, int32_t all_phases) {
     CHECK_CTX();
     if (!d_y || !d_f) return fail(TNLM_E_INVALID_ARG, "null device pointer");
-    TIMED(ctx, K_FBP, launch_fbp(ctx->dg, d_y, ctx->hfilt, ctx->cw, ctx->Q, d_f, all_phases ? 1 : 0, (float)ctx->geom.sad_mm,
-               ctx->stream));
-    CHECK_LAUNCH();
-    return TNLM_OK;
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    TIMED(E, K_FBP,
+          launch_fbp(E->batch, E->st_ffilt, all_phases ? E->st_fbp_all : E->st_fbp_ph, d_y, E->hfilt, E->cw, E->Q, d_f,
+                     all_phases ? 1 : 0, E->stream));
+    return last_launch();
 }
 
-extern "C" tnlm_status tnlm_data_step(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, float *d_g) {
+extern "C" tnlm_status tnlm_data_step(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f,
+                                      float *d_g) {
     CHECK_CTX();
     if (!d_y || !d_w || !d_f || !d_g) return fail(TNLM_E_INVALID_ARG, "null device pointer");
     if (d_f == d_g) return fail(TNLM_E_INVALID_ARG, "d_f and d_g must not alias");
-    if (ctx->prm.m1_cgls > 0) TIMED(ctx, K_VECTOR, launch_sqrt(d_w, ctx->cb.sw, ctx->nsino, ctx->stream));
-    enqueue_data_step(ctx, d_y, d_w, d_f, ctx->zero());
-    TIMED(ctx, K_VECTOR, launch_copy(ctx->cb.u, d_g, ctx->nimg, ctx->zero(), ctx->stream));
-    CHECK_LAUNCH();
-    return TNLM_OK;
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    if (E->prm.m1_cgls > 0) TIMED(E, K_VECTOR, launch_sqrt(d_w, E->cb.sw, E->nsino, E->stream));
+    enqueue_data_step(E, E->batch, d_y, d_w, d_f);
+    TIMED(E, K_VECTOR, launch_copy(E->cb.u, d_g, E->nimg, E->stream));
+    return last_launch();
 }
 
 extern "C" tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, const float *d_value, const float *d_g,
@@ -438,41 +782,123 @@ extern "C" tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, cons
     if (!d_guide || !d_value || !d_g || !d_out) return fail(TNLM_E_INVALID_ARG, "null device pointer");
     if (d_out == d_guide || d_out == d_value || d_out == d_g)
         return fail(TNLM_E_INVALID_ARG, "d_out must not alias an input");
-    TIMED(ctx, K_REGULARIZE, launch_regularize(ctx->rs, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr, nullptr, nullptr, ctx->stream));
-    CHECK_LAUNCH();
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    if (E->prm.ssd_mode == TNLM_SSD_BF16_MFMA)
+        TIMED(E, K_REGULARIZE,
+              launch_regularize_mfma(E->batch, E->st_reg, E->rp, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr,
+                                     nullptr, E->stream));
+    else
+        TIMED(E, K_REGULARIZE,
+              launch_regularize(E->batch, E->st_reg, E->rp, E->rows_per_lane, d_guide, d_value, d_g, d_out,
+                                clamp ? 1 : 0, nullptr, nullptr, E->stream));
+    return last_launch();
+}
+
+static tnlm_status timing_enable(Engine *E, int32_t enable) {
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    for (auto &r : E->recs) {
+        E->pool.push_back(r.a);
+        E->pool.push_back(r.b);
+    }
+    E->recs.clear();
+    E->timing = enable != 0;
+    return TNLM_OK;
+}
+
+static tnlm_status timing_read(Engine *E, double *ms, int32_t *launches) {
+    if (!ms || !launches) return fail(TNLM_E_INVALID_ARG, "null output array");
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    for (int k = 0; k < TNLM_KIND_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : E->recs) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.kind] += t;
+        launches[r.kind] += 1;
+        E->pool.push_back(r.a);
+        E->pool.push_back(r.b);
+    }
+    E->recs.clear();
     return TNLM_OK;
 }
 
 extern "C" tnlm_status tnlm_timing_enable(tnlm_ctx *ctx, int32_t enable) {
     CHECK_CTX();
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    for (auto &r : ctx->recs) {
-        ctx->pool.push_back(r.a);
-        ctx->pool.push_back(r.b);
-    }
-    ctx->recs.clear();
-    ctx->timing = enable != 0;
-    return TNLM_OK;
+    return timing_enable(&ctx->e, enable);
 }
 
 extern "C" tnlm_status tnlm_timing_read(tnlm_ctx *ctx, double *ms, int32_t *launches) {
     CHECK_CTX();
-    if (!ms || !launches) return fail(TNLM_E_INVALID_ARG, "null output array");
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < TNLM_KIND_COUNT; ++k) {
-        ms[k] = 0.0;
-        launches[k] = 0;
-    }
-    for (auto &r : ctx->recs) {
-        float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
-        ms[r.kind] += t;
-        launches[r.kind] += 1;
-        ctx->pool.push_back(r.a);
-        ctx->pool.push_back(r.b);
-    }
-    ctx->recs.clear();
+    return timing_read(&ctx->e, ms, launches);
+}
+
+extern "C" tnlm_status tnlm_autotune(tnlm_ctx *ctx, int32_t *rows_per_lane, float *ms) {
+    CHECK_CTX();
+    return engine_autotune(&ctx->e, rows_per_lane, ms);
+}
+
+// ---- batch of slices (ragged sizes)
+extern "C" tnlm_status tnlm_batch_init(tnlm_batch **out, int32_t n_slices, const tnlm_geometry *geoms,
+                                       const tnlm_params *params, void *stream) {
+    if (!out) return fail(TNLM_E_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (n_slices < 1 || !geoms) return fail(TNLM_E_INVALID_ARG, "need n_slices >= 1 and geometries");
+    std::unique_ptr<tnlm_batch> b(new (std::nothrow) tnlm_batch());
+    if (!b) return fail(TNLM_E_OOM, "host allocation failed");
+    tnlm_status s = engine_init(b->e, n_slices, geoms, params, stream);
+    if (s != TNLM_OK) return s;
+    Engine &E = b->e;
+    HIP_TRY(E.alloc(&E.Y, E.nsino));
+    HIP_TRY(E.alloc(&E.Wt, E.nsino));
+    HIP_TRY(E.alloc(&E.F, E.nimg));
+    *out = b.release();
     return TNLM_OK;
+}
+
+extern "C" void tnlm_batch_destroy(tnlm_batch *b) { delete b; }
+
+extern "C" tnlm_status tnlm_batch_solve(tnlm_batch *bt, const float *const *d_y, const float *const *d_w,
+                                        float *const *d_f, int32_t *out_iters, float *out_rel,
+                                        tnlm_status *out_status) {
+    if (!bt) return fail(TNLM_E_INVALID_ARG, "null batch");
+    if (!d_y || !d_w || !d_f) return fail(TNLM_E_INVALID_ARG, "null pointer array");
+    Engine *E = &bt->e;
+    for (int s = 0; s < E->ns; ++s)
+        if (!d_y[s] || !d_w[s] || !d_f[s])
+            return fail(TNLM_E_INVALID_ARG, "null device pointer for slice " + std::to_string(s));
+    hipStream_t st = E->stream;
+    for (int s = 0; s < E->ns; ++s) {
+        const SliceDesc &d = E->sl[s];
+        const size_t nsn = (size_t)d.N * d.V * d.B, ni = (size_t)d.N * d.L * d.L;
+        HIP_TRY(hipMemcpyAsync(E->Y + d.sino0, d_y[s], nsn * sizeof(float), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(E->Wt + d.sino0, d_w[s], nsn * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (E->prm.init == TNLM_INIT_USER)
+            HIP_TRY(hipMemcpyAsync(E->F + d.img0, d_f[s], ni * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    tnlm_status s = engine_solve(E, E->Y, E->Wt, E->F);
+    if (s != TNLM_OK) return s;
+    for (int k = 0; k < E->ns; ++k) {
+        const SliceDesc &d = E->sl[k];
+        HIP_TRY(hipMemcpyAsync(d_f[k], E->F + d.img0, (size_t)d.N * d.L * d.L * sizeof(float), hipMemcpyDeviceToDevice,
+                               st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    s = engine_results(E, out_iters, out_rel, out_status);
+    if (s < 0) return fail(s, "a slice failed (see out_status)");
+    return s;
+}
+
+extern "C" tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable) {
+    if (!b) return fail(TNLM_E_INVALID_ARG, "null batch");
+    return timing_enable(&b->e, enable);
+}
+
+extern "C" tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches) {
+    if (!b) return fail(TNLM_E_INVALID_ARG, "null batch");
+    return timing_read(&b->e, ms, launches);
 }
 
 extern "C" const char *tnlm_status_string(tnlm_status s) {

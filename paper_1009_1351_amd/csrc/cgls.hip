@@ -9,155 +9,211 @@
 // same order, so every block gets the same scalar) and apply the updates.
 // A phase whose ||P_n^T r||^2 or ||P_n s||^2 is exactly zero stops: a = 0 from
 // then on, u unchanged.
+//
+// Work items are (slice, phase, chunk) over the batch's slice table; a chunk
+// covers a contiguous range of the phase's image (and sinogram) elements.
 #include "devutil.h"
 #include "internal.h"
 
 namespace tnlm {
 
-__global__ void k_sqrt(const float *__restrict__ w, float *__restrict__ sw, size_t n) {
-    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; k < n; k += (size_t)gridDim.x * blockDim.x) sw[k] = sqrtf(fmaxf(w[k], 0.0f));
+constexpr int kMaxVecBlocks = 64;
+
+int vec_blocks(const SliceDesc &s) {
+    const long long n = (long long)s.L * s.L + (long long)s.V * s.B;
+    return (int)std::max<long long>(1, std::min<long long>((n + 4 * kBlock - 1) / (4 * kBlock), kMaxVecBlocks));
 }
+
+struct VecItem {
+    int s, i, chunk, nchunk;
+};
+
+__device__ __forceinline__ VecItem vec_item(const Stage &st, int ns, int gb, const SliceDesc *sl, SliceDesc &sd) {
+    VecItem it;
+    it.s = find_slice(st.pre, ns, gb);
+    sd = sl[it.s];
+    const int lb = gb - st.pre[it.s];
+    it.nchunk = (st.pre[it.s + 1] - st.pre[it.s]) / sd.N;
+    it.i = lb / it.nchunk;
+    it.chunk = lb - it.i * it.nchunk;
+    return it;
+}
+
+__device__ __forceinline__ void chunk_range(long long n, int chunk, int nchunk, long long &lo, long long &hi) {
+    const long long per = (n + nchunk - 1) / nchunk;
+    lo = std::min(n, (long long)chunk * per);
+    hi = std::min(n, lo + per);
+}
+
+__global__ void k_sqrt(const float *__restrict__ w, float *__restrict__ sw, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        sw[k] = sqrtf(fmaxf(w[k], 0.0f));
+}
+
+static int flat_blocks(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 4096)); }
 
 void launch_sqrt(const float *w, float *sw, size_t n, hipStream_t st) {
-    int nb = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
-    k_sqrt<<<nb, kBlock, 0, st>>>(w, sw, n);
+    k_sqrt<<<flat_blocks(n), kBlock, 0, st>>>(w, sw, n);
 }
 
-__global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n, const int *skip) {
-    if (skip_now(skip)) return;
-    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; k < n; k += (size_t)gridDim.x * blockDim.x) b[k] = a[k];
+__global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        b[k] = a[k];
 }
 
-void launch_copy(const float *src, float *dst, size_t n, const int *skip, hipStream_t st) {
-    int nb = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
-    k_copy<<<nb, kBlock, 0, st>>>(src, dst, n, skip);
+void launch_copy(const float *src, float *dst, size_t n, hipStream_t st) {
+    k_copy<<<flat_blocks(n), kBlock, 0, st>>>(src, dst, n);
+}
+
+// Per-slice copy (image- or sinogram-shaped), skipping stopped slices.
+__global__ __launch_bounds__(kBlock) void k_copy_skip(Batch bt, Stage st, int image, const float *__restrict__ a,
+                                                      float *__restrict__ b) {
+    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+        SliceDesc sd;
+        const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
+        if (bt.skip && bt.skip[it.s]) continue;
+        const long long n = image ? (long long)sd.L * sd.L : (long long)sd.V * sd.B;
+        const long long base = (image ? sd.img0 : sd.sino0) + (long long)it.i * n;
+        long long lo, hi;
+        chunk_range(n, it.chunk, it.nchunk, lo, hi);
+        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) b[base + k] = a[base + k];
+    }
+}
+
+void launch_copy_skip(const Batch &b, const Stage &st, bool image, const float *src, float *dst, hipStream_t strm) {
+    k_copy_skip<<<st.grid, kBlock, 0, strm>>>(b, st, image ? 1 : 0, src, dst);
 }
 
 // Step m: a = gamma/||q||^2, u += a s (image part), r -= a q and rw = sw r (sinogram part).
-__global__ __launch_bounds__(kBlock) void k_cgls_update(int nimg, int nsino, const double *__restrict__ gpart,
-                                                        int nbp, const double *__restrict__ qpart, int npp,
-                                                        int *__restrict__ stop, int m, int N,
-                                                        float *__restrict__ u, const float *__restrict__ s,
-                                                        float *__restrict__ r, const float *__restrict__ q,
-                                                        float *__restrict__ rw, const float *__restrict__ sw,
-                                                        const int *skip) {
+__global__ __launch_bounds__(kBlock) void k_cgls_update(Batch bt, Stage st, CglsBufs cb, int m, int gsel) {
     __shared__ double sh[kBlock];
-    if (skip_now(skip)) return;
-    const int i = blockIdx.y;
-    const double gamma = block_sum_array(gpart + (size_t)i * nbp, nbp, sh);
-    const double qq = block_sum_array(qpart + (size_t)i * npp, npp, sh);
-    const int stopped_before = m > 0 ? stop[(size_t)m * N + i] : 0;
-    const int stopped = stopped_before || !(gamma > 0.0) || !(qq > 0.0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) stop[(size_t)(m + 1) * N + i] = stopped;
-    if (stopped) return;
-    const float a = (float)(gamma / qq);
-    const size_t tot = (size_t)nimg + nsino;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < tot; k += (size_t)gridDim.x * kBlock) {
-        if (k < (size_t)nimg) {
-            const size_t e = (size_t)i * nimg + k;
-            u[e] = fmaf(a, s[e], u[e]);
-        } else {
-            const size_t e = (size_t)i * nsino + (k - nimg);
-            const float rv = fmaf(-a, q[e], r[e]);
-            r[e] = rv;
-            rw[e] = sw[e] * rv;
+    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+        SliceDesc sd;
+        const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
+        if (bt.skip && bt.skip[it.s]) continue;
+        const double gamma = block_sum_array(cb.gpart[gsel] + sd.gp0 + (long long)it.i * sd.nbp, sd.nbp, sh);
+        const double qq = block_sum_array(cb.qpart + sd.qp0 + (long long)it.i * sd.npp, sd.npp, sh);
+        const int gp = sd.phase0 + it.i;
+        const int stopped_before = m > 0 ? cb.stop[(long long)m * cb.nphase + gp] : 0;
+        const int stopped = stopped_before || !(gamma > 0.0) || !(qq > 0.0);
+        if (it.chunk == 0 && threadIdx.x == 0) cb.stop[(long long)(m + 1) * cb.nphase + gp] = stopped;
+        if (stopped) continue;
+        const float a = (float)(gamma / qq);
+        const long long nimg = (long long)sd.L * sd.L, nsino = (long long)sd.V * sd.B;
+        long long lo, hi;
+        chunk_range(nimg + nsino, it.chunk, it.nchunk, lo, hi);
+        const long long ib = sd.img0 + (long long)it.i * nimg, sbase = sd.sino0 + (long long)it.i * nsino;
+        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) {
+            if (k < nimg) {
+                cb.u[ib + k] = fmaf(a, cb.s[ib + k], cb.u[ib + k]);
+            } else {
+                const long long e = sbase + (k - nimg);
+                const float rv = fmaf(-a, cb.q[e], cb.r[e]);
+                cb.r[e] = rv;
+                cb.rw[e] = cb.sw[e] * rv;
+            }
         }
     }
 }
 
-static int vec_blocks(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>((n + 4 * kBlock - 1) / (4 * kBlock), 512)); }
-
-void launch_cgls_update(const DevGeom &g, CglsBufs &b, int m, int gsel, const int *skip, hipStream_t st) {
-    const int nimg = g.L * g.L, nsino = g.V * g.B;
-    dim3 grid(vec_blocks((size_t)nimg + nsino), g.N);
-    k_cgls_update<<<grid, kBlock, 0, st>>>(nimg, nsino, b.gpart[gsel], b.nbp, b.qpart, b.npp, b.stop, m, g.N,
-                                           b.u, b.s, b.r, b.q, b.rw, b.sw, skip);
+void launch_cgls_update(const Batch &b, const Stage &st, CglsBufs &cb, int m, int gsel, hipStream_t strm) {
+    k_cgls_update<<<st.grid, kBlock, 0, strm>>>(b, st, cb, m, gsel);
 }
 
 // s = t + (gamma_new / gamma_old) s
-__global__ __launch_bounds__(kBlock) void k_cgls_direction(int nimg, const double *__restrict__ gold,
-                                                           const double *__restrict__ gnew, int nbp,
-                                                           const int *__restrict__ stop, int m, int N,
-                                                           float *__restrict__ s, const float *__restrict__ t,
-                                                           const int *skip) {
+__global__ __launch_bounds__(kBlock) void k_cgls_direction(Batch bt, Stage st, CglsBufs cb, int m, int gold,
+                                                           int gnew) {
     __shared__ double sh[kBlock];
-    if (skip_now(skip)) return;
-    const int i = blockIdx.y;
-    if (stop[(size_t)(m + 1) * N + i]) return;
-    const double go = block_sum_array(gold + (size_t)i * nbp, nbp, sh);
-    const double gn = block_sum_array(gnew + (size_t)i * nbp, nbp, sh);
-    const float bc = (float)(gn / go);
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < (size_t)nimg; k += (size_t)gridDim.x * kBlock) {
-        const size_t e = (size_t)i * nimg + k;
-        s[e] = fmaf(bc, s[e], t[e]);
+    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+        SliceDesc sd;
+        const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
+        if (bt.skip && bt.skip[it.s]) continue;
+        if (cb.stop[(long long)(m + 1) * cb.nphase + sd.phase0 + it.i]) continue;
+        const double go = block_sum_array(cb.gpart[gold] + sd.gp0 + (long long)it.i * sd.nbp, sd.nbp, sh);
+        const double gn = block_sum_array(cb.gpart[gnew] + sd.gp0 + (long long)it.i * sd.nbp, sd.nbp, sh);
+        const float bc = (float)(gn / go);
+        const long long nimg = (long long)sd.L * sd.L;
+        long long lo, hi;
+        chunk_range(nimg, it.chunk, it.nchunk, lo, hi);
+        const long long ib = sd.img0 + (long long)it.i * nimg;
+        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) cb.s[ib + k] = fmaf(bc, cb.s[ib + k], cb.t[ib + k]);
     }
 }
 
-void launch_cgls_direction(const DevGeom &g, CglsBufs &b, int m, int gsel_old, int gsel_new, const int *skip,
-                           hipStream_t st) {
-    const int nimg = g.L * g.L;
-    dim3 grid(vec_blocks(nimg), g.N);
-    k_cgls_direction<<<grid, kBlock, 0, st>>>(nimg, b.gpart[gsel_old], b.gpart[gsel_new], b.nbp, b.stop, m, g.N,
-                                              b.s, b.t, skip);
+void launch_cgls_direction(const Batch &b, const Stage &st, CglsBufs &cb, int m, int gold, int gnew,
+                           hipStream_t strm) {
+    k_cgls_direction<<<st.grid, kBlock, 0, strm>>>(b, st, cb, m, gold, gnew);
 }
 
 // Eq. 4 helpers: tmp = w (P f - y); g = f - (1/beta) P^T tmp
-__global__ void k_weighted_resid(size_t n, const float *__restrict__ q, const float *__restrict__ y,
-                                 const float *__restrict__ w, float *__restrict__ out, const int *skip) {
-    if (skip_now(skip)) return;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        out[k] = w[k] * (q[k] - y[k]);
+__global__ __launch_bounds__(kBlock) void k_weighted_resid(Batch bt, Stage st, const float *__restrict__ q,
+                                                           const float *__restrict__ y, const float *__restrict__ w,
+                                                           float *__restrict__ out) {
+    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+        SliceDesc sd;
+        const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
+        if (bt.skip && bt.skip[it.s]) continue;
+        const long long n = (long long)sd.V * sd.B, base = sd.sino0 + (long long)it.i * n;
+        long long lo, hi;
+        chunk_range(n, it.chunk, it.nchunk, lo, hi);
+        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) out[base + k] = w[base + k] * (q[base + k] - y[base + k]);
+    }
 }
 
-void launch_weighted_resid(const DevGeom &g, const float *q, const float *y, const float *w, float *out,
-                           const int *skip, hipStream_t st) {
-    size_t n = (size_t)g.N * g.V * g.B;
-    k_weighted_resid<<<vec_blocks(n), kBlock, 0, st>>>(n, q, y, w, out, skip);
+void launch_weighted_resid(const Batch &b, const Stage &st, const float *q, const float *y, const float *w,
+                           float *out, hipStream_t strm) {
+    k_weighted_resid<<<st.grid, kBlock, 0, strm>>>(b, st, q, y, w, out);
 }
 
-__global__ void k_gradient_step(size_t n, const float *__restrict__ f, const float *__restrict__ bp, float inv_beta,
-                                float *__restrict__ g, const int *skip) {
-    if (skip_now(skip)) return;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        g[k] = fmaf(-inv_beta, bp[k], f[k]);
+__global__ __launch_bounds__(kBlock) void k_gradient_step(Batch bt, Stage st, const float *__restrict__ f,
+                                                          const float *__restrict__ bp, float inv_beta,
+                                                          float *__restrict__ g) {
+    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+        SliceDesc sd;
+        const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
+        if (bt.skip && bt.skip[it.s]) continue;
+        const long long n = (long long)sd.L * sd.L, base = sd.img0 + (long long)it.i * n;
+        long long lo, hi;
+        chunk_range(n, it.chunk, it.nchunk, lo, hi);
+        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) g[base + k] = fmaf(-inv_beta, bp[base + k], f[base + k]);
+    }
 }
 
-void launch_gradient_step(const DevGeom &g, const float *f, const float *bp, float inv_beta, float *gout,
-                          const int *skip, hipStream_t st) {
-    size_t n = (size_t)g.N * g.L * g.L;
-    k_gradient_step<<<vec_blocks(n), kBlock, 0, st>>>(n, f, bp, inv_beta, gout, skip);
+void launch_gradient_step(const Batch &b, const Stage &st, const float *f, const float *bp, float inv_beta,
+                          float *gout, hipStream_t strm) {
+    k_gradient_step<<<st.grid, kBlock, 0, strm>>>(b, st, f, bp, inv_beta, gout);
 }
 
-// Outer-loop bookkeeping (one block): relative update from the regulariser's
-// partials [nblocks][2] = (sum (f_new - f_old)^2, sum f_new^2), history,
+// Outer-loop bookkeeping, one block per slice: relative update from the
+// regulariser's partials (sum (f_new - f_old)^2, sum f_new^2), history,
 // iteration counter, convergence / non-finite stop flag.
-__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblocks, float tol,
+__global__ __launch_bounds__(kBlock) void k_finalize(Batch bt, const double *__restrict__ partials, float tol,
                                                      float *__restrict__ hist, int *__restrict__ counter,
                                                      int *__restrict__ done, const int *__restrict__ nonfinite,
-                                                     int max_outer, const int *skip) {
+                                                     int max_outer) {
     __shared__ double sh[kBlock];
-    if (skip_now(skip)) return;
+    const int s = blockIdx.x;
+    if (bt.skip && bt.skip[s]) return;
+    const SliceDesc sd = bt.sl[s];
     double dd = 0.0, nn = 0.0;
-    for (int k = threadIdx.x; k < nblocks; k += kBlock) {
-        dd += partials[2 * k];
-        nn += partials[2 * k + 1];
+    for (int k = threadIdx.x; k < sd.nrb; k += kBlock) {
+        dd += partials[2 * ((long long)sd.rp0 + k)];
+        nn += partials[2 * ((long long)sd.rp0 + k) + 1];
     }
     dd = block_sum_256(dd, sh);
     nn = block_sum_256(nn, sh);
     if (threadIdx.x == 0) {
         const double rel = sqrt(dd) / fmax(sqrt(nn), 1e-30);
-        const int k = *counter;
-        if (k < max_outer) hist[k] = (float)rel;
-        *counter = k + 1;
-        if ((tol > 0.0f && rel < (double)tol) || *nonfinite) *done = 1;
+        const int k = counter[s];
+        if (k < max_outer) hist[(long long)s * max_outer + k] = (float)rel;
+        counter[s] = k + 1;
+        if ((tol > 0.0f && rel < (double)tol) || nonfinite[s]) done[s] = 1;
     }
 }
 
-void launch_finalize(const double *partials, int nblocks, float tol, float *hist, int *counter, int *done,
-                     int *nonfinite, int max_outer, const int *skip, hipStream_t st) {
-    k_finalize<<<1, kBlock, 0, st>>>(partials, nblocks, tol, hist, counter, done, nonfinite, max_outer, skip);
+void launch_finalize(const Batch &b, const double *relpart, float tol, float *hist, int *counter, int *done,
+                     const int *nonfinite, int max_outer, hipStream_t strm) {
+    k_finalize<<<b.ns, kBlock, 0, strm>>>(b, relpart, tol, hist, counter, done, nonfinite, max_outer);
 }
 
 __global__ void k_check_finite(const float *__restrict__ a, size_t n, int *flag) {
@@ -166,7 +222,15 @@ __global__ void k_check_finite(const float *__restrict__ a, size_t n, int *flag)
 }
 
 void launch_check_finite(const float *a, size_t n, int *flag, hipStream_t st) {
-    k_check_finite<<<vec_blocks(n), kBlock, 0, st>>>(a, n, flag);
+    k_check_finite<<<flat_blocks(n), kBlock, 0, st>>>(a, n, flag);
+}
+
+__global__ void k_fill_int(int *a, int n, int v) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) a[k] = v;
+}
+
+void launch_fill_int(int *a, int n, int v, hipStream_t st) {
+    if (n > 0) k_fill_int<<<std::max(1, std::min((n + kBlock - 1) / kBlock, 1024)), kBlock, 0, st>>>(a, n, v);
 }
 
 }  // namespace tnlm

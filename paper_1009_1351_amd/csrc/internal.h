@@ -1,72 +1,143 @@
 // Internal declarations shared by the library's HIP translation units.
+//
+// Every kernel works on a *batch* of slices described by a slice table: each
+// slice has its own image side L, views V, bins B and offsets into the batch's
+// contiguous arrays. A kernel launch covers the blocks of all slices; blocks
+// find their slice by binary search in a per-stage prefix table and loop over
+// work items (persistent grid-stride loop). A single slice is a batch of one.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
-#include <algorithm>
 
 #include "../../include/tnlm.h"
 
 namespace tnlm {
 
-// Per-slice device geometry: everything a projector kernel needs.
-struct DevGeom {
+struct SliceDesc {
     int N, L, V, B;
     float D;         // pixel size (mm)
     float X0;        // -L*D/2: left/bottom edge of the image square
     float dgamma;    // angular bin pitch
     float ucenter;   // (B-1)/2 - det_offset: bin coordinate of the central ray
-    const float4 *rt0;   // [N][V][B] plane tables (Ax, Bx, Ay, By): T_x(k) = fma(k, Ax, Bx)
-    const float4 *rt1;   // [N][V][B] (ox, oy, ux, uy): ray point nearest the centre, direction
-    const float4 *vt;    // [N][V] (sx, sy, cos th, sin th)
+    long long ray0;  // first ray of this slice in the ray tables ([N][V][B])
+    long long view0; // first view in the view table ([N][V])
+    long long img0;  // first element in image-shaped arrays ([N][L][L])
+    long long sino0; // first element in sinogram-shaped arrays ([N][V][B])
+    int gp0, qp0, rp0;   // first partial slot in gpart / qpart / relpart
+    int nbp, npp, nrb;   // partial slots per phase (transpose, projector) and per slice (regulariser)
+    int hf0, cw0;        // first entry of this slice's FBP filter taps (2B-1) and cosine weights (B)
+    int phase0;          // first global phase index of this slice
 };
 
-struct RegShape {
-    int N, L, patch, window;
+// Per-stage block prefix: blocks of slice s are [pre[s], pre[s+1]).
+struct Stage {
+    const int *pre;   // device [ns + 1]
+    int total;        // pre[ns]
+    int grid;         // persistent grid size
+};
+
+struct Batch {
+    int ns = 0;
+    const SliceDesc *sl = nullptr;   // device [ns]
+    const float4 *rt0 = nullptr;     // rays: (Ax, Bx, Ay, By), T_x(k) = fma(k, Ax, Bx)
+    const float4 *rt1 = nullptr;     // rays: (ox, oy, ux, uy)
+    const float4 *vt = nullptr;      // views: (sx, sy, cos th, sin th)
+    const int *skip = nullptr;       // device [ns] per-slice stop flags (nullable: run all)
+};
+
+struct RegParams {
+    int patch, window;
     float h, mu_hat;
 };
 
+// Block index -> (slice, local block). Block-uniform.
+__device__ __forceinline__ int find_slice(const int *pre, int ns, int gb) {
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= gb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent loop order: the 8 XCDs receive consecutive hardware block ids in
+// turn; give each XCD a contiguous range of work items so that the blocks
+// sharing an XCD (and its L2) work on the same slices and phases.
+__device__ __forceinline__ void xcd_range(int total, int &first, int &stride, int &count) {
+    const int nx = 8;
+    const int g = (int)gridDim.x;
+    if (g < nx) {   // fewer blocks than XCDs: plain grid-stride order
+        first = (int)blockIdx.x;
+        stride = g;
+        count = total;
+        return;
+    }
+    const int x = (int)blockIdx.x % nx;
+    const int per_x = (g - x + nx - 1) / nx;          // blocks on this XCD
+    const int k = (int)blockIdx.x / nx;                // rank within the XCD
+    const int chunk = (total + nx - 1) / nx;
+    const int lo = std::min(total, x * chunk), hi = std::min(total, lo + chunk);
+    first = lo + k;
+    stride = per_x;
+    count = hi;
+}
+
 // ---- projector (proj.hip)
 enum ProjMode { PROJ_PLAIN = 0, PROJ_RESID = 1, PROJ_SCALED = 2 };
-int proj_blocks_per_phase(const DevGeom &g);
-void launch_project(const DevGeom &g, int mode, const float *f, const float *y, const float *sw, float *out,
-                    float *out2, double *partials, const int *skip, hipStream_t st);
-int bp_blocks_per_phase(const DevGeom &g);
-void launch_backproject(const DevGeom &g, const float *q, float *f, double *partials, const int *skip,
-                        hipStream_t st);
+int proj_blocks(const SliceDesc &s);
+int bp_blocks(const SliceDesc &s);
+void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *y, const float *sw,
+                    float *out, float *out2, double *partials, hipStream_t strm);
+void launch_backproject(const Batch &b, const Stage &st, const float *q, float *f, double *partials,
+                        hipStream_t strm);
 
 // ---- CGLS vector work (cgls.hip)
 struct CglsBufs {
-    float *u, *s, *t;        // [N][L][L]
-    float *r, *q, *rw, *sw;  // [N][V][B]
-    double *gpart[2];        // [N][nbp]: partial ||P^T r||^2 (ping-pong)
-    double *qpart;           // [N][npp]: partial ||P s||^2
-    int *stop;               // [M1+1][N] CGLS stop flags
-    int nbp, npp;
+    float *u, *s, *t;           // image-shaped
+    float *r, *q, *rw, *sw;     // sinogram-shaped
+    double *gpart[2];           // partial ||P^T r||^2 (ping-pong)
+    double *qpart;              // partial ||P s||^2
+    int *stop;                  // [M1+1][total phases] CGLS stop flags
+    int nphase;                 // total phases in the batch
 };
+int vec_blocks(const SliceDesc &s);   // per phase
 void launch_sqrt(const float *w, float *sw, size_t n, hipStream_t st);
-void launch_copy(const float *src, float *dst, size_t n, const int *skip, hipStream_t st);
-void launch_cgls_update(const DevGeom &g, CglsBufs &b, int m, int gsel, const int *skip, hipStream_t st);
-void launch_cgls_direction(const DevGeom &g, CglsBufs &b, int m, int gsel_old, int gsel_new, const int *skip,
-                           hipStream_t st);
-void launch_gradient_step(const DevGeom &g, const float *f, const float *bp, float inv_beta, float *gout,
-                          const int *skip, hipStream_t st);
-void launch_weighted_resid(const DevGeom &g, const float *q, const float *y, const float *w, float *out,
-                           const int *skip, hipStream_t st);
-void launch_finalize(const double *partials, int nblocks, float tol, float *hist, int *counter, int *done,
-                     int *nonfinite, int max_outer, const int *skip, hipStream_t st);
+void launch_copy(const float *src, float *dst, size_t n, hipStream_t st);
+void launch_copy_skip(const Batch &b, const Stage &st, bool image, const float *src, float *dst, hipStream_t strm);
+void launch_cgls_update(const Batch &b, const Stage &st, CglsBufs &cb, int m, int gsel, hipStream_t strm);
+void launch_cgls_direction(const Batch &b, const Stage &st, CglsBufs &cb, int m, int gold, int gnew,
+                           hipStream_t strm);
+void launch_weighted_resid(const Batch &b, const Stage &st, const float *q, const float *y, const float *w,
+                           float *out, hipStream_t strm);
+void launch_gradient_step(const Batch &b, const Stage &st, const float *f, const float *bp, float inv_beta,
+                          float *gout, hipStream_t strm);
+void launch_finalize(const Batch &b, const double *relpart, float tol, float *hist, int *counter, int *done,
+                     const int *nonfinite, int max_outer, hipStream_t strm);
 void launch_check_finite(const float *a, size_t n, int *flag, hipStream_t st);
+void launch_fill_int(int *a, int n, int v, hipStream_t st);
 
 // ---- TNLM regulariser (tnlm_reg.hip)
-int reg_blocks(const RegShape &s);
+int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane);
 bool reg_supported(int patch, int window);
-void launch_regularize(const RegShape &s, const float *guide, const float *value, const float *g, float *out,
-                       int clamp, double *relpart, int *nonfinite, const int *skip, hipStream_t st);
+void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int rows_per_lane,
+                       const float *guide, const float *value, const float *g, float *out, int clamp,
+                       double *relpart, int *nonfinite, hipStream_t strm);
+
+// ---- regulariser with BF16 MFMA patch distances (tnlm_reg_mfma.hip)
+int reg_mfma_blocks(const SliceDesc &s);
+bool reg_mfma_supported(int patch, int window);
+void launch_regularize_mfma(const Batch &b, const Stage &st, const RegParams &p, const float *guide,
+                            const float *value, const float *g, float *out, int clamp, double *relpart,
+                            int *nonfinite, hipStream_t strm);
 
 // ---- FBP (fbp.hip)
-void launch_fbp(const DevGeom &g, const float *y, const float *hfilt, const float *cosw, float *Q, float *f,
-                int all_phases, float sad, hipStream_t st);
+void launch_fbp(const Batch &b, const Stage &filt, const Stage &bp, const float *y, const float *hfilt,
+                const float *cosw, float *Q, float *f, int all_phases, hipStream_t strm);
+int fbp_bp_blocks(const SliceDesc &s, int all_phases);
 
 }  // namespace tnlm

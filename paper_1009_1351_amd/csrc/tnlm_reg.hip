@@ -7,8 +7,9 @@
 // with y over the W x W window truncated to the image and patch pixels outside
 // the image replaced by the nearest edge pixel.
 //
-// CDNA4 mapping (one 256-thread block per output tile of 32 rows x (32-2S)
-// columns of one phase; S = (d-1)/2, R = (W-1)/2):
+// CDNA4 mapping (one 256-thread block per output tile of 4*BY rows x (32-2S)
+// columns of one phase; S = (d-1)/2, R = (W-1)/2, BY = output rows per lane;
+// blocks loop persistently over the tiles of every slice of a batch):
 //   * guide/value tiles of both neighbour phases, with the window and patch
 //     halo, are staged once in LDS (edge-clamped at load time);
 //   * wave w handles neighbour j = w & 1 and half of the window rows
@@ -31,18 +32,15 @@
 namespace tnlm {
 
 struct RegArgs {
-    int N, L, R;
+    int R;
     float nk;        // -log2(e) / h^2
     float cs, cn;    // 1/(1+mu), mu/(2mu+2)
     const float *guide, *value, *g;
     float *out;
     int clamp;
     double *relpart;
-    int *nonfinite;
-    const int *skip;
+    int *nonfinite;  // [ns]
 };
-
-constexpr int kBY = 8;   // output rows per lane
 
 // Value of x held by lane (l + K) of the same 16-lane row; 0 outside the row.
 template <int K>
@@ -114,20 +112,31 @@ __device__ __forceinline__ void merge(float nk, float Dm1, float num1, float den
     Dm = m;
 }
 
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
+template <int S, int kBY>
+__global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs a) {
     extern __shared__ float lds[];
     __shared__ double shred[kBlock];
-    if (skip_now(a.skip)) return;
     constexpr int TW = 32 - 2 * S, TH = 4 * kBY, NR = kBY + 2 * S;
-    const int R = a.R, L = a.L, N = a.N;
+    const int R = a.R;
     const int TCW = 32 + 2 * R, TRH = TH + 2 * S + 2 * R, TS = TCW * TRH;
-    const int i = blockIdx.z;
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-    const int nbr0 = (i - 1 + N) % N, nbr1 = (i + 1) % N;
     const bool same = a.value == a.guide;
+    int first, stride, count;
+    xcd_range(st.total, first, stride, count);
+    for (int gb = first; gb < count; gb += stride) {
+    const int sidx = find_slice(st.pre, bt.ns, gb);
+    if (bt.skip && bt.skip[sidx]) continue;
+    const SliceDesc sd = bt.sl[sidx];
+    const int L = sd.L, N = sd.N;
+    const int ntx = (L + TW - 1) / TW, nty = (L + TH - 1) / TH;
+    int lb = gb - st.pre[sidx];
+    const int tile_local = lb % (ntx * nty);
+    const int i = lb / (ntx * nty);
+    const int x0 = (tile_local % ntx) * TW, y0 = (tile_local / ntx) * TH;
+    const int nbr0 = (i - 1 + N) % N, nbr1 = (i + 1) % N;
     const size_t plane = (size_t)L * L;
+    const float *guide = a.guide + sd.img0, *value = a.value + sd.img0;
 
+    __syncthreads();   // LDS reuse across work items
     float *tg0 = lds, *tg1 = lds + TS;
     float *tv0 = same ? tg0 : lds + 2 * TS, *tv1 = same ? tg1 : lds + 3 * TS;
     const int col0 = x0 - S - R, row0 = y0 - S - R;
@@ -135,11 +144,11 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
         const int tr = e / TCW, tc = e - tr * TCW;
         const int gr = min(max(row0 + tr, 0), L - 1), gc = min(max(col0 + tc, 0), L - 1);
         const size_t off = (size_t)gr * L + gc;
-        tg0[e] = a.guide[nbr0 * plane + off];
-        tg1[e] = a.guide[nbr1 * plane + off];
+        tg0[e] = guide[nbr0 * plane + off];
+        tg1[e] = guide[nbr1 * plane + off];
         if (!same) {
-            tv0[e] = a.value[nbr0 * plane + off];
-            tv1[e] = a.value[nbr1 * plane + off];
+            tv0[e] = value[nbr0 * plane + off];
+            tv1[e] = value[nbr1 * plane + off];
         }
     }
 
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
 
     float gia[NR], gib[NR];
     {
-        const float *gi = a.guide + (size_t)i * plane;
+        const float *gi = guide + (size_t)i * plane;
         const int ca = min(max(xa, 0), L - 1), cb = min(max(xa + 1, 0), L - 1);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
@@ -250,8 +259,8 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
     __syncthreads();
     double dd = 0.0, nn = 0.0;
     if (wave == 0) {
-        const float *gi = a.g + (size_t)i * plane;
-        float *oi = a.out + (size_t)i * plane;
+        const float *gi = a.g + sd.img0 + (size_t)i * plane;
+        float *oi = a.out + sd.img0 + (size_t)i * plane;
         bool bad = false;
 #pragma unroll
         for (int o = 0; o < kBY; ++o) {
@@ -282,23 +291,24 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(RegArgs a) {
                 oi[e] = u;
             }
         }
-        if (bad && a.nonfinite) *a.nonfinite = 1;
+        if (bad && a.nonfinite) a.nonfinite[sidx] = 1;
     }
     if (a.relpart) {
         dd = block_sum_256(dd, shred);
         nn = block_sum_256(nn, shred);
         if (threadIdx.x == 0) {
-            const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            const long long blk = (long long)sd.rp0 + lb;
             a.relpart[2 * blk] = dd;
             a.relpart[2 * blk + 1] = nn;
         }
     }
+    }   // work items
 }
 
 static int tile_w(int patch) { return 32 - 2 * (patch / 2); }
 
-int reg_blocks(const RegShape &s) {
-    const int tw = tile_w(s.patch), th = 4 * kBY;
+int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane) {
+    const int tw = tile_w(patch), th = 4 * rows_per_lane;
     return ((s.L + tw - 1) / tw) * ((s.L + th - 1) / th) * s.N;
 }
 
@@ -306,23 +316,33 @@ bool reg_supported(int patch, int window) {
     return patch >= 3 && patch <= 9 && (patch & 1) && window >= 3 && window <= 21 && (window & 1);
 }
 
-static size_t reg_lds_bytes(const RegShape &s, bool same) {
-    const int S = s.patch / 2, R = s.window / 2;
-    const size_t ts = (size_t)(32 + 2 * R) * (4 * kBY + 2 * S + 2 * R);
+static size_t reg_lds_bytes(const RegParams &p, int BY, bool same) {
+    const int S = p.patch / 2, R = p.window / 2;
+    const size_t ts = (size_t)(32 + 2 * R) * (4 * BY + 2 * S + 2 * R);
     const size_t tiles = (same ? 2 : 4) * ts;
-    const size_t merge = 3 * 2 * 64 * 2 * kBY + 64 * 2 * kBY;
+    const size_t merge = 3 * 2 * 64 * 2 * BY + 64 * 2 * BY;
     return std::max(tiles, merge) * sizeof(float);
 }
 
-void launch_regularize(const RegShape &s, const float *guide, const float *value, const float *g, float *out,
-                       int clamp, double *relpart, int *nonfinite, const int *skip, hipStream_t st) {
+template <int BY>
+static void launch_by(const Batch &b, const Stage &st, int S, RegArgs a, size_t lds, hipStream_t strm) {
+    switch (S) {
+        case 1: k_tnlm_reg<1, BY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        case 2: k_tnlm_reg<2, BY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        case 3: k_tnlm_reg<3, BY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        default: k_tnlm_reg<4, BY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+    }
+}
+
+void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int rows_per_lane,
+                       const float *guide, const float *value, const float *g, float *out, int clamp,
+                       double *relpart, int *nonfinite, hipStream_t strm) {
+    if (st.total == 0) return;
     RegArgs a;
-    a.N = s.N;
-    a.L = s.L;
-    a.R = s.window / 2;
-    a.nk = (float)(-1.4426950408889634 / ((double)s.h * (double)s.h));
-    a.cs = (float)(1.0 / (1.0 + (double)s.mu_hat));
-    a.cn = (float)((double)s.mu_hat / (2.0 * (double)s.mu_hat + 2.0));
+    a.R = p.window / 2;
+    a.nk = (float)(-1.4426950408889634 / ((double)p.h * (double)p.h));
+    a.cs = (float)(1.0 / (1.0 + (double)p.mu_hat));
+    a.cn = (float)((double)p.mu_hat / (2.0 * (double)p.mu_hat + 2.0));
     a.guide = guide;
     a.value = value;
     a.g = g;
@@ -330,16 +350,9 @@ void launch_regularize(const RegShape &s, const float *guide, const float *value
     a.clamp = clamp;
     a.relpart = relpart;
     a.nonfinite = nonfinite;
-    a.skip = skip;
-    const int tw = tile_w(s.patch), th = 4 * kBY;
-    dim3 grid((s.L + tw - 1) / tw, (s.L + th - 1) / th, s.N);
-    const size_t lds = reg_lds_bytes(s, value == guide);
-    switch (s.patch / 2) {
-        case 1: k_tnlm_reg<1><<<grid, kBlock, lds, st>>>(a); break;
-        case 2: k_tnlm_reg<2><<<grid, kBlock, lds, st>>>(a); break;
-        case 3: k_tnlm_reg<3><<<grid, kBlock, lds, st>>>(a); break;
-        default: k_tnlm_reg<4><<<grid, kBlock, lds, st>>>(a); break;
-    }
+    const size_t lds = reg_lds_bytes(p, rows_per_lane, value == guide);
+    if (rows_per_lane == 4) launch_by<4>(b, st, p.patch / 2, a, lds, strm);
+    else launch_by<8>(b, st, p.patch / 2, a, lds, strm);
 }
 
 }  // namespace tnlm

@@ -131,6 +131,13 @@ class Recon:
         check(nat.lib.tnlm_timing_read(self._ctx, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(nat.KIND_NAMES)}
 
+    def autotune(self):
+        """Pick the regulariser tile height on the device (see tnlm_autotune)."""
+        rpl = C.c_int32(0)
+        ms = (C.c_float * 2)()
+        check(nat.lib.tnlm_autotune(self._ctx, C.byref(rpl), ms))
+        return rpl.value, (ms[0], ms[1])
+
     def history(self):
         n = self.params["max_outer"]
         buf = (C.c_float * n)()
@@ -139,4 +146,77 @@ class Recon:
         return np.array(buf[:cnt.value], dtype=np.float64)
 
 
-__all__ = ["Recon", "TnlmError"]
+def _geom_struct(geom, angles_keep):
+    ang = np.ascontiguousarray(np.asarray(geom.view_angles(), dtype=np.float64))
+    angles_keep.append(ang)
+    return nat.Geometry(geom.n_phases, geom.L, float(geom.pixel_mm), geom.n_views, geom.n_bins, float(geom.sad_mm),
+                        float(geom.sdd_mm), float(geom.dgamma), float(geom.det_offset_bins),
+                        ang.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+class Batch:
+    """Many slices (uneven L, V, B) solved together: tnlm_batch_init / tnlm_batch_solve."""
+
+    def __init__(self, geoms, *, patch=7, window=15, h=0.007, mu_hat=0.5, beta=1.0, m1=3, m2=1, max_outer=50,
+                 tol=0.0, init="fbp", device=None):
+        self.geoms = list(geoms)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._keep = []
+        arr = (nat.Geometry * len(self.geoms))(*[_geom_struct(g, self._keep) for g in self.geoms])
+        p = nat.Params(int(patch), int(window), float(h), float(mu_hat), float(beta), int(m1), int(m2),
+                       int(max_outer), float(tol), nat.INIT_FBP_ALL if init == "fbp" else nat.INIT_USER,
+                       nat.SSD_FP32)
+        self.max_outer = int(max_outer)
+        self._b = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(nat.lib.tnlm_batch_init(C.byref(self._b), len(self.geoms), arr, C.byref(p),
+                                          C.c_void_p(_stream_ptr(self.device))))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            nat.lib.tnlm_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_images(self):
+        return [torch.zeros((g.n_phases, g.L, g.L), dtype=torch.float32, device=self.device) for g in self.geoms]
+
+    def solve(self, ys, ws, fs=None):
+        """Returns (fs, iterations[n], last relative updates[n], statuses[n], worst status)."""
+        n = len(self.geoms)
+        fs = self.new_images() if fs is None else fs
+        for g, y, w, f in zip(self.geoms, ys, ws, fs):
+            for t, shape in ((y, (g.n_phases, g.n_views, g.n_bins)), (w, (g.n_phases, g.n_views, g.n_bins)),
+                             (f, (g.n_phases, g.L, g.L))):
+                if t.dtype != torch.float32 or t.device != self.device or tuple(t.shape) != shape \
+                        or not t.is_contiguous():
+                    raise ValueError(f"batch tensor must be contiguous float32 {shape} on {self.device}")
+        P = C.c_void_p * n
+        yp = P(*[t.data_ptr() for t in ys])
+        wp = P(*[t.data_ptr() for t in ws])
+        fp = P(*[t.data_ptr() for t in fs])
+        iters = (C.c_int32 * n)()
+        rel = (C.c_float * n)()
+        sts = (C.c_int * n)()
+        st = nat.lib.tnlm_batch_solve(self._b, yp, wp, fp, iters, rel, sts)
+        if st < 0 and all(x >= 0 for x in sts):
+            check(st)
+        return fs, list(iters), list(rel), list(sts), st
+
+    def timing(self, enable: bool):
+        check(nat.lib.tnlm_batch_timing_enable(self._b, int(bool(enable))))
+
+    def timing_read(self):
+        k = len(nat.KIND_NAMES)
+        ms = (C.c_double * k)()
+        cnt = (C.c_int32 * k)()
+        check(nat.lib.tnlm_batch_timing_read(self._b, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(nat.KIND_NAMES)}
+
+
+__all__ = ["Recon", "Batch", "TnlmError"]

@@ -1,0 +1,123 @@
+"""Batched engine (many slices of uneven L, V, B in one launch per stage,
+one outer iteration per replayed hipGraph) and the tile autotuner.
+
+A batch must give, per slice, bitwise the result of the single-slice context
+(same kernels, same per-slice arithmetic and reduction order), match the FP64
+oracle within the trajectory bar, and let converged slices drop out while the
+others go on.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import announce, f32, recon_for, rel_l2_per_phase, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+SHAPES = [dict(L=48, V=40, B=64, I0=1e4), dict(L=64, V=30, B=96, I0=3e4), dict(L=40, V=56, B=72, I0=5e5),
+          dict(L=33, V=25, B=61, I0=2e4)]
+
+
+def make_cases(K, tol=0.0):
+    return [synth.make_case("C1", slice_index=s, K=K, tol=tol, patch=5, window=9, randomize=True, **sh)
+            for s, sh in enumerate(SHAPES)]
+
+
+def batch_for(cases, **kw):
+    from paper_1009_1351_amd import Batch
+    c = cases[0]
+    return Batch([c.geom for c in cases], patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat,
+                 max_outer=c.max_outer, tol=c.tol, **kw)
+
+
+def test_batch_equals_single_slices_bitwise():
+    cases = make_cases(K=4)
+    bt = batch_for(cases)
+    ys = [to_dev(c.y) for c in cases]
+    ws = [to_dev(c.w) for c in cases]
+    fs, iters, rel, sts, st = bt.solve(ys, ws)
+    assert st == 0 and iters == [4] * len(cases)
+    for c, y, w, f in zip(cases, ys, ws, fs):
+        rc = recon_for(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat, max_outer=4)
+        f1, k, _, _ = rc.solve(y, w)
+        assert torch.equal(f, f1), c.name
+
+
+def test_batch_matches_oracle(orc):
+    cases = make_cases(K=3)
+    bt = batch_for(cases)
+    fs, iters, _, _, st = bt.solve([to_dev(c.y) for c in cases], [to_dev(c.w) for c in cases])
+    for c, f in zip(cases[:2], fs[:2]):
+        prm = orc.case_params(c, h=float(np.float32(c.h)), mu_hat=float(np.float32(c.mu_hat)))
+        ref, _, _, _ = orc.solve(orc.Geometry(c.geom), prm, f32(c.y), f32(c.w))
+        err = rel_l2_per_phase(to_host(f), ref)
+        announce(f"batch vs oracle {c.name}: {err.max():.2e}")
+        assert err.max() < 1e-4
+
+
+def test_batch_slices_stop_independently():
+    tol = 3e-3
+    cases = make_cases(K=40, tol=tol)
+    bt = batch_for(cases)
+    fs, iters, rel, sts, st = bt.solve([to_dev(c.y) for c in cases], [to_dev(c.w) for c in cases])
+    assert all(s == 0 for s in sts) and all(r < tol for r in rel)
+    singles = []
+    for c in cases:
+        rc = recon_for(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat, max_outer=40, tol=tol)
+        _, k, _, _ = rc.solve(to_dev(c.y), to_dev(c.w))
+        singles.append(k)
+    announce(f"iterations to tol: batch {iters}, single {singles}")
+    assert iters == singles
+    assert len(set(iters)) > 1, "the test wants slices that converge at different iterations"
+
+
+def test_graph_replay_matches_direct_launches(monkeypatch):
+    case = synth.make_case("C1", K=5)
+    y, w = to_dev(case.y), to_dev(case.w)
+    kw = dict(patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat, max_outer=5)
+    a, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
+    monkeypatch.setenv("TNLM_NO_GRAPH", "1")
+    b, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
+    assert torch.equal(a, b)
+    # several solves replay the same graph; eager work and syncs in between
+    rc = recon_for(case.geom, **kw)
+    monkeypatch.delenv("TNLM_NO_GRAPH")
+    rc2 = recon_for(case.geom, **kw)
+    f = rc2.new_image()
+    for _ in range(3):
+        out, _, _, _ = rc2.solve(y, w, f)
+        torch.cuda.synchronize()
+        _ = (out * 2).sum().item()
+        assert torch.equal(out, a)
+
+
+def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
+    monkeypatch.setenv("TNLM_AUTOTUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    case = synth.make_case("C1", K=3)
+    y, w = to_dev(case.y), to_dev(case.w)
+    kw = dict(patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat, max_outer=3)
+    ref, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
+    rc = recon_for(case.geom, **kw)
+    rpl, ms = rc.autotune()
+    announce(f"autotune: rows/lane {rpl}, ms {ms}")
+    assert rpl in (4, 8) and all(m > 0 for m in ms)
+    out, _, _, _ = rc.solve(y, w)
+    assert torch.equal(out, ref)
+    assert (tmp_path / "tune.jsonl").exists()
+    # a new context of the same class starts from the cached choice and agrees
+    out2, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
+    assert torch.equal(out2, ref)
+    for rows in ("4", "8"):
+        monkeypatch.setenv("TNLM_ROWS_PER_LANE", rows)
+        o, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
+        assert torch.equal(o, ref), rows
