@@ -1,17 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the TNLM 4DCT reconstruction hot path on one MI355X.
 
-Workload (one "step"): the 256x256 paper-size slice in its three dose cases,
-each a full solve -- FBP of all phases' views, then 50 outer iterations of
-(3 CGLS steps -> patch weights over a 15x15 window of phases i+-1 with 7x7
-patches -> one Gauss-Jacobi sweep -> positivity):
+Timed step: the 256x256 paper-size slice in its three dose cases, solved
+together as one batch by the batched engine -- FBP of all phases' views, then
+50 outer iterations of (3 CGLS steps -> patch weights over a 15x15 window of
+phases i+-1 with 7x7 patches -> one Gauss-Jacobi sweep -> positivity):
     a: 360 views/phase, I0 = 2e4     b: 60 views/phase, I0 = 1e6
     c: 60 views/phase, I0 = 2e4      (10 phases, 512 bins, fan-beam arc)
 Inputs are seeded synthetic phantoms (nested ellipses, moving tumour,
 analytic line integrals, Poisson noise) resident in HBM before timing.
 
 Metric: phase-pixel*iterations per second = sum over slices of N*L^2*K / wall
-seconds, plus wall seconds per 10-phase slice. Prints one JSON line.
+seconds. Also reported: the same workload with BF16-MFMA patch distances,
+and -- when trained warm-start weights are present -- wall seconds per
+10-phase slice to a relative update of 1e-4 for the learned warm start +
+batched engine against the plain path (cold start, one slice at a time).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -30,6 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 OPS_PER_CROSSING = 8                       # projector: ops per ray-pixel crossing (matrix entry)
 OPS_PER_PAIR = 10                          # regulariser: ops per (pixel, candidate) pair
+WEIGHTS = os.path.join(ROOT, "paper_1009_1351_amd", "weights", "warmstart_c5.npz")
 
 
 def log(msg):
@@ -70,7 +75,7 @@ KERNEL_SOURCES = {
 }
 
 
-def traffic_for(kernel: str, launches_per_step: float):
+def traffic_for(kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
@@ -104,6 +109,43 @@ def cpu_baseline(case_fn):
                       f"bins, from the FBP image; {dt:.1f} s"}
 
 
+def learned_vs_plain(torch, dev, n_slices, tol=1e-4):
+    """Wall seconds per slice to tol: plain (cold start, one slice at a time)
+    against the learned warm start + batched engine, on 512^2 slices."""
+    import synth
+    from paper_1009_1351_amd import Batch, Recon
+    from paper_1009_1351_amd.warmstart import WarmStartNet, warm_starts
+    net = WarmStartNet(phases=10, base=32)
+    net.load_weights(WEIGHTS)
+    cases = [synth.make_case("C5eval", slice_index=20_000 + k) for k in range(n_slices)]
+    c0 = cases[0]
+    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, max_outer=500, tol=tol, device=dev)
+    ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(dev) for c in cases]
+    ws = [torch.from_numpy(np.asarray(c.w, np.float32)).to(dev) for c in cases]
+    plain = [Recon.from_geometry(c.geom, **kw) for c in cases]
+    recons = [Recon.from_geometry(c.geom, patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, device=dev)
+              for c in cases]
+    bt = Batch([c.geom for c in cases], init="user", **kw)
+    plain[0].solve(ys[0], ws[0])   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_p = [rc.solve(y, w)[1] for rc, y, w in zip(plain, ys, ws)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    f0s, used = warm_starts(recons, ys, ws, net)
+    bt.solve(ys, ws, [f.clone() for f in f0s])   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f0s, used = warm_starts(recons, ys, ws, net)
+    _, it_l, _, st_l, _ = bt.solve(ys, ws, f0s)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, to relative update {tol}",
+            "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters_mean": float(np.mean(it_p)),
+            "learned_batched_wall_s_per_slice": t_learned / n_slices, "learned_iters_mean": float(np.mean(it_l)),
+            "warm_start_used": int(sum(used)), "all_reached_tol": bool(all(s == 0 for s in st_l))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=50, help="outer iterations per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and warm-start legs")
+    ap.add_argument("--learned-slices", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -120,33 +164,28 @@ def main():
 
     import torch
     import synth
-    from paper_1009_1351_amd import Recon
+    from paper_1009_1351_amd import Batch
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     names = ["C2a", "C2b", "C2c"]
-    cases = {n: synth.make_case(n, K=a.iters) for n in names}
+    cases = [synth.make_case(n, K=a.iters) for n in names]
     log("inputs generated")
-    runs = []
-    for n in names:
-        c = cases[n]
-        rc = Recon.from_geometry(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat, m1=c.m1,
-                                 m2=c.m2, max_outer=c.max_outer, tol=0.0)
-        y = torch.from_numpy(c.y.astype(np.float32)).to(dev)
-        w = torch.from_numpy(c.w.astype(np.float32)).to(dev)
-        f = rc.new_image()
-        runs.append((n, c, rc, y, w, f))
+    c0 = cases[0]
+    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, m1=c0.m1, m2=c0.m2, max_outer=a.iters,
+              tol=0.0, device=dev)
+    bt = Batch([c.geom for c in cases], **kw)
+    ys = [torch.from_numpy(c.y.astype(np.float32)).to(dev) for c in cases]
+    ws = [torch.from_numpy(c.w.astype(np.float32)).to(dev) for c in cases]
+    fs = bt.new_images()
     torch.cuda.synchronize()
 
-    def step():
-        done = 0
-        for n, c, rc, y, w, f in runs:
-            _, k, _, st = rc.solve(y, w, f)
-            done += c.geom.n_phases * c.geom.L ** 2 * k
-        return done
+    def step(b):
+        _, iters, _, st, _ = b.solve(ys, ws, fs)
+        return sum(c.geom.n_phases * c.geom.L ** 2 * k for c, k in zip(cases, iters))
 
     for _ in range(a.warmup):
-        step()
+        step(bt)
     log("warmup done")
     if a.calib_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -154,50 +193,63 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _, _, rc, _, _, _ in runs:
-        rc.timing(True)
+    bt.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     units = 0
     for s in range(a.steps):
-        units += step()
+        units += step(bt)
         log(f"step {s + 1}/{a.steps}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    per_kind = {}
-    algo = {"project": 0.0, "backproject": 0.0, "regularize": 0.0}
-    for n, c, rc, _, _, _ in runs:
-        t = rc.timing_read()
-        rc.timing(False)
-        for k, (ms, cnt) in t.items():
-            tot = per_kind.setdefault(k, [0.0, 0])
-            tot[0] += ms
-            tot[1] += cnt
-        nz = crossings(c.geom)
-        algo["project"] += t["project"][1] * nz * OPS_PER_CROSSING
-        algo["backproject"] += t["backproject"][1] * nz * OPS_PER_CROSSING
-        algo["regularize"] += t["regularize"][1] * pairs(c) * OPS_PER_PAIR
+    t = bt.timing_read()
+    bt.timing(False)
+    per_kind = {k: list(v) for k, v in t.items()}
+    nz = sum(crossings(c.geom) for c in cases)
+    npairs = sum(pairs(c) for c in cases)
+    algo = {"project": t["project"][1] * nz * OPS_PER_CROSSING,
+            "backproject": t["backproject"][1] * nz * OPS_PER_CROSSING,
+            "regularize": t["regularize"][1] * npairs * OPS_PER_PAIR}
     dom = max(algo, key=lambda k: per_kind[k][0])
     ms_tot, launches = per_kind[dom]
     achieved = algo[dom] / (ms_tot * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
             "unit": "TOP/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
             "avg_launch_ms": round(ms_tot / max(launches, 1), 4),
-            "traffic": traffic_for(dom, launches / a.steps)}
+            "algorithmic_ops_per_launch": algo[dom] / max(launches, 1),
+            "traffic": traffic_for(dom)}
     value = units / dt
-    slices = len(runs) * a.steps
+    slices = len(cases) * a.steps
     out = {
         "metric": "phase-pixel*iters/s", "value": value, "unit": "phase-pixel*iters/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "C2: 1 slice x 10 phases, 256x256, 512 bins, doses a (360 views, I0 2e4), "
-                               "b (60 views, I0 1e6), c (60 views, I0 2e4); patch 7, window 15, M1 3, M2 1; "
-                               f"{a.iters} outer iterations from the FBP of all phases",
-                   "slices_per_step": len(runs), "wall_s_per_slice": dt / slices,
-                   "parallelism": "single GPU"},
-        "kernel_ms": {k: round(v[0] / a.steps, 3) for k, v in per_kind.items()},
+        "config": {"workload": "C2: 3 slices x 10 phases, 256x256, 512 bins, doses a (360 views, I0 2e4), "
+                               "b (60 views, I0 1e6), c (60 views, I0 2e4) in one batch; patch 7, window 15, "
+                               f"M1 3, M2 1; {a.iters} outer iterations from the FBP of all phases",
+                   "slices_per_step": len(cases), "wall_s_per_slice": dt / slices, "parallelism": "single GPU"},
+        "kernel_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in per_kind.items()},
         "roofline": roof,
     }
+    if not a.no_extras:
+        log("BF16-MFMA leg ...")
+        bb = Batch([c.geom for c in cases], ssd_mode="bf16_mfma", **kw)
+        step(bb)
+        torch.cuda.synchronize()
+        bb.timing(True)
+        t0 = time.perf_counter()
+        u = step(bb)
+        torch.cuda.synchronize()
+        d2 = time.perf_counter() - t0
+        tb = bb.timing_read()
+        out["bf16_mfma"] = {"value": u / d2, "regularize_ms_per_step": round(tb["regularize"][0], 3),
+                            "fp32_regularize_ms_per_step": round(per_kind["regularize"][0] / a.steps, 3)}
+        bb.close()
+        if os.path.exists(WEIGHTS):
+            log("learned warm start leg ...")
+            out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
+        else:
+            out["learned_vs_plain"] = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(lambda n: synth.make_case(n, K=a.iters))

@@ -211,6 +211,44 @@ tnlm_status tnlm_batch_solve(tnlm_batch *b, const float *const *d_y, const float
 tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable);
 tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches);
 
+/*
+ * Data term of Eq. 1 for the current iterate: out = sum_i (P_i f_i - y_i)^T S^-1
+ * (P_i f_i - y_i) with S^-1 = diag(w) (double, host). Synchronises.
+ */
+tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, double *out);
+
+/*
+ * Learned warm start: an encoder-decoder network (4 levels with b, 2b, 4b, 8b
+ * channels, two 3x3 convolutions + ReLU per level, 2x2 average pooling,
+ * nearest 2x upsampling, skip concatenation, 1x1 head, residual to the input)
+ * mapping the N per-phase FBP images of a slice ([n][N][H][W] float32, image
+ * units) to an estimate of the converged TNLM images (same shape), used as
+ * f^(0) of the TNLM algorithm box. BF16 weights and activations, FP32
+ * accumulation, FP32 master weights and Adam moments; trained and run by the
+ * library's own kernels. H and W must be multiples of 8. input_scale
+ * multiplies the images before the network (e.g. 50 for attenuations ~0.02/mm).
+ * Parameters: all weights [Cout][Cin][k][k] layer by layer, then all biases.
+ */
+typedef struct tnlm_cnn tnlm_cnn;
+tnlm_status tnlm_cnn_create(tnlm_cnn **out, int32_t phases, int32_t base_channels, uint64_t seed, float input_scale,
+                            void *stream);
+void tnlm_cnn_destroy(tnlm_cnn *net);
+int64_t tnlm_cnn_num_params(const tnlm_cnn *net);
+tnlm_status tnlm_cnn_get_params(tnlm_cnn *net, float *host, int64_t n);
+tnlm_status tnlm_cnn_set_params(tnlm_cnn *net, const float *host, int64_t n);
+/* inference: d_out = network(d_in), both [n][N][H][W] float32 device. Async. */
+tnlm_status tnlm_cnn_forward(tnlm_cnn *net, const float *d_in, float *d_out, int32_t n, int32_t H, int32_t W);
+/* MSE loss (in input_scale units) and its gradient (host_grad nullable, num_params floats). Synchronises. */
+tnlm_status tnlm_cnn_loss_grad(tnlm_cnn *net, const float *d_in, const float *d_target, int32_t n, int32_t H, int32_t W,
+                               double *loss, float *host_grad, int64_t ngrad);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) on the MSE loss; *loss = loss before the step. Synchronises. */
+tnlm_status tnlm_cnn_train_step(tnlm_cnn *net, const float *d_in, const float *d_target, int32_t n, int32_t H,
+                                int32_t W, float lr, double *loss);
+/* checkpoint = parameters, Adam moments, step count; load validates shape and finiteness. */
+tnlm_status tnlm_cnn_save(tnlm_cnn *net, const char *path);
+tnlm_status tnlm_cnn_load(tnlm_cnn *net, const char *path);
+const char *tnlm_cnn_last_error(void);
+
 const char *tnlm_status_string(tnlm_status s);
 const char *tnlm_last_error(void);
 

@@ -59,6 +59,20 @@ for _name, _args, _res in [
                           C.POINTER(C.c_int)], C.c_int),
     ("tnlm_batch_timing_enable", [_P, C.c_int32], C.c_int),
     ("tnlm_batch_timing_read", [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
+    ("tnlm_data_cost", [_P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
+    ("tnlm_cnn_create", [C.POINTER(_P), C.c_int32, C.c_int32, C.c_uint64, C.c_float, _P], C.c_int),
+    ("tnlm_cnn_destroy", [_P], None),
+    ("tnlm_cnn_num_params", [_P], C.c_int64),
+    ("tnlm_cnn_get_params", [_P, _FP, C.c_int64], C.c_int),
+    ("tnlm_cnn_set_params", [_P, _FP, C.c_int64], C.c_int),
+    ("tnlm_cnn_forward", [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    ("tnlm_cnn_loss_grad", [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), _FP, C.c_int64],
+     C.c_int),
+    ("tnlm_cnn_train_step", [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.POINTER(C.c_double)],
+     C.c_int),
+    ("tnlm_cnn_save", [_P, C.c_char_p], C.c_int),
+    ("tnlm_cnn_load", [_P, C.c_char_p], C.c_int),
+    ("tnlm_cnn_last_error", [], C.c_char_p),
     ("tnlm_status_string", [C.c_int], C.c_char_p),
     ("tnlm_last_error", [], C.c_char_p),
 ]:
@@ -71,7 +85,10 @@ def exported_symbols():
     return ["tnlm_recon_init", "tnlm_destroy", "tnlm_step", "tnlm_solve", "tnlm_get_history", "tnlm_project",
             "tnlm_backproject", "tnlm_fbp", "tnlm_data_step", "tnlm_regularize", "tnlm_timing_enable",
             "tnlm_timing_read", "tnlm_autotune", "tnlm_batch_init", "tnlm_batch_destroy", "tnlm_batch_solve",
-            "tnlm_batch_timing_enable", "tnlm_batch_timing_read", "tnlm_status_string", "tnlm_last_error"]
+            "tnlm_batch_timing_enable", "tnlm_batch_timing_read", "tnlm_data_cost", "tnlm_cnn_create",
+            "tnlm_cnn_destroy", "tnlm_cnn_num_params", "tnlm_cnn_get_params", "tnlm_cnn_set_params",
+            "tnlm_cnn_forward", "tnlm_cnn_loss_grad", "tnlm_cnn_train_step", "tnlm_cnn_save", "tnlm_cnn_load",
+            "tnlm_cnn_last_error", "tnlm_status_string", "tnlm_last_error"]
 
 
 KIND_NAMES = ["project", "backproject", "regularize", "vector", "fbp", "other"]
@@ -86,6 +103,12 @@ class TnlmError(RuntimeError):
 def check(status: int) -> int:
     if status < 0:
         raise TnlmError(status, _lib.tnlm_last_error().decode())
+    return status
+
+
+def check_cnn(status: int) -> int:
+    if status < 0:
+        raise TnlmError(status, _lib.tnlm_cnn_last_error().decode())
     return status
 
 

@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtnlm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "proj.hip", "cgls.hip", "tnlm_reg.hip", "tnlm_reg_mfma.hip", "fbp.hip"]
+SOURCES = ["api.hip", "proj.hip", "cgls.hip", "tnlm_reg.hip", "tnlm_reg_mfma.hip", "fbp.hip", "cnn.hip", "cnn_net.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

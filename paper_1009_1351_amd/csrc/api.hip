@@ -69,6 +69,7 @@ struct Engine {
     CglsBufs cb{};
     float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
+    double *cost_part = nullptr;   // [1024] partials of the data-term reduction
     int *flags = nullptr;   // [4][ns]: done, counter, nonfinite, spare
     float *hist = nullptr;  // [ns][max_outer]
     float *Y = nullptr, *Wt = nullptr, *F = nullptr;   // batch copies of caller arrays
@@ -381,6 +382,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     }
     HIP_TRY(E.alloc(&E.relpart, 2 * (size_t)rpp));
     HIP_TRY(E.alloc(&E.flags, 4 * (size_t)ns));
+    HIP_TRY(E.alloc(&E.cost_part, 1024));
     HIP_TRY(E.alloc(&E.hist, (size_t)ns * params->max_outer));
     HIP_TRY(hipMemset(E.flags, 0, 4 * ns * sizeof(int)));
     HIP_TRY(hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
@@ -792,6 +794,24 @@ extern "C" tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, cons
         TIMED(E, K_REGULARIZE,
               launch_regularize(E->batch, E->st_reg, E->rp, E->rows_per_lane, d_guide, d_value, d_g, d_out,
                                 clamp ? 1 : 0, nullptr, nullptr, E->stream));
+    return last_launch();
+}
+
+extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f,
+                                      double *out) {
+    CHECK_CTX();
+    if (!d_y || !d_w || !d_f || !out) return fail(TNLM_E_INVALID_ARG, "null pointer");
+    Engine *E = &ctx->e;
+    E->cur = E->stream;
+    TIMED(E, K_PROJECT,
+          launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, nullptr, nullptr, E->cb.q, nullptr, nullptr, E->stream));
+    const int nb = launch_wsq_sum(E->cb.q, d_y, d_w, E->nsino, E->cost_part, E->stream);
+    std::vector<double> part(nb);
+    HIP_TRY(hipMemcpyAsync(part.data(), E->cost_part, nb * sizeof(double), hipMemcpyDeviceToHost, E->stream));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    double s = 0.0;
+    for (double v : part) s += v;
+    *out = s;
     return last_launch();
 }
 

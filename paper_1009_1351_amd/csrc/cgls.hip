@@ -225,6 +225,25 @@ void launch_check_finite(const float *a, size_t n, int *flag, hipStream_t st) {
     k_check_finite<<<flat_blocks(n), kBlock, 0, st>>>(a, n, flag);
 }
 
+// sum of w (q - y)^2: per-block partials (FP64), at most 1024 blocks
+__global__ __launch_bounds__(kBlock) void k_wsq_sum(const float *__restrict__ q, const float *__restrict__ y,
+                                                    const float *__restrict__ w, size_t n, double *__restrict__ part) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const double d = (double)q[k] - (double)y[k];
+        s += (double)w[k] * d * d;
+    }
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+int launch_wsq_sum(const float *q, const float *y, const float *w, size_t n, double *part, hipStream_t st) {
+    const int nb = std::min(flat_blocks(n), 1024);
+    k_wsq_sum<<<nb, kBlock, 0, st>>>(q, y, w, n, part);
+    return nb;
+}
+
 __global__ void k_fill_int(int *a, int n, int v) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) a[k] = v;
 }

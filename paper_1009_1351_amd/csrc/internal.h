@@ -120,6 +120,7 @@ void launch_finalize(const Batch &b, const double *relpart, float tol, float *hi
                      const int *nonfinite, int max_outer, hipStream_t strm);
 void launch_check_finite(const float *a, size_t n, int *flag, hipStream_t st);
 void launch_fill_int(int *a, int n, int v, hipStream_t st);
+int launch_wsq_sum(const float *q, const float *y, const float *w, size_t n, double *part, hipStream_t st);
 
 // ---- TNLM regulariser (tnlm_reg.hip)
 int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane);

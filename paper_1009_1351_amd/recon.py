@@ -15,6 +15,11 @@ from . import _native as nat
 from ._native import TnlmError, check
 
 
+def _norm_device(device):
+    d = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    return torch.device("cuda", torch.cuda.current_device()) if d.index is None else d
+
+
 def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -26,7 +31,7 @@ class Recon:
                  det_offset_bins=0.25, patch=7, window=15, h=0.007, mu_hat=0.5, beta=1.0, m1=3, m2=1,
                  max_outer=50, tol=0.0, init="fbp", ssd_mode="fp32", device=None):
         self.N, self.L, self.V, self.B = int(n_phases), int(L), int(n_views), int(n_bins)
-        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.device = _norm_device(device)
         ang = np.ascontiguousarray(np.asarray(view_angles, dtype=np.float64).reshape(self.N, self.V))
         self._angles = ang
         g = nat.Geometry(self.N, self.L, float(pixel_mm), self.V, self.B, float(sad_mm), float(sdd_mm),
@@ -158,14 +163,14 @@ class Batch:
     """Many slices (uneven L, V, B) solved together: tnlm_batch_init / tnlm_batch_solve."""
 
     def __init__(self, geoms, *, patch=7, window=15, h=0.007, mu_hat=0.5, beta=1.0, m1=3, m2=1, max_outer=50,
-                 tol=0.0, init="fbp", device=None):
+                 tol=0.0, init="fbp", ssd_mode="fp32", device=None):
         self.geoms = list(geoms)
-        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.device = _norm_device(device)
         self._keep = []
         arr = (nat.Geometry * len(self.geoms))(*[_geom_struct(g, self._keep) for g in self.geoms])
         p = nat.Params(int(patch), int(window), float(h), float(mu_hat), float(beta), int(m1), int(m2),
                        int(max_outer), float(tol), nat.INIT_FBP_ALL if init == "fbp" else nat.INIT_USER,
-                       nat.SSD_FP32)
+                       nat.SSD_FP32 if ssd_mode == "fp32" else nat.SSD_BF16_MFMA)
         self.max_outer = int(max_outer)
         self._b = C.c_void_p()
         with torch.cuda.device(self.device):

@@ -1,0 +1,208 @@
+"""Learned warm start for the TNLM solve (Python face of tnlm_cnn_*).
+
+The network maps the N per-phase FBP images of a slice to an estimate of its
+converged TNLM solution; that estimate replaces the FBP of all phases as
+f^(0) of the TNLM algorithm box. It is trained on pairs the method itself
+produces (per-phase FBP, TNLM solved to a relative-update tolerance). All
+computation runs in the library's kernels; this module marshals arguments
+and orchestrates.
+
+Fallback rule: the warm start is used for a slice only if the network output
+is finite and its data term (Eq. 1, first part) is not larger than that of
+the FBP of all phases; otherwise the slice starts cold.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+
+import numpy as np
+import torch
+
+from . import _native as nat
+from ._native import check, check_cnn
+from .recon import _norm_device
+
+
+class WarmStartNet:
+    def __init__(self, phases=10, base=32, seed=0, scale=50.0, device=None):
+        self.device = _norm_device(device)
+        self.phases, self.base, self.scale = int(phases), int(base), float(scale)
+        self._n = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check_cnn(nat.lib.tnlm_cnn_create(C.byref(self._n), self.phases, self.base, int(seed), self.scale,
+                                              C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_n", None) is not None and self._n.value:
+            nat.lib.tnlm_cnn_destroy(self._n)
+            self._n = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(nat.lib.tnlm_cnn_num_params(self._n))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, np.float32)
+        check_cnn(nat.lib.tnlm_cnn_get_params(self._n, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        check_cnn(nat.lib.tnlm_cnn_set_params(self._n, p.ctypes.data_as(C.POINTER(C.c_float)), p.size))
+
+    def _chk(self, x, name):
+        if x.dtype != torch.float32 or x.device != self.device or x.dim() != 4 or not x.is_contiguous() \
+                or x.shape[1] != self.phases:
+            raise ValueError(f"{name} must be a contiguous float32 [n][{self.phases}][H][W] tensor on {self.device}")
+        return C.c_void_p(x.data_ptr())
+
+    def forward(self, x, out=None):
+        out = torch.empty_like(x) if out is None else out
+        n, _, H, W = x.shape
+        check_cnn(nat.lib.tnlm_cnn_forward(self._n, self._chk(x, "x"), self._chk(out, "out"), n, H, W))
+        return out
+
+    def loss_grad(self, x, t, want_grad=True):
+        n, _, H, W = x.shape
+        loss = C.c_double(0.0)
+        g = np.empty(self.num_params, np.float32) if want_grad else None
+        check_cnn(nat.lib.tnlm_cnn_loss_grad(self._n, self._chk(x, "x"), self._chk(t, "t"), n, H, W, C.byref(loss),
+                                             g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None,
+                                             self.num_params if want_grad else 0))
+        return loss.value, g
+
+    def train_step(self, x, t, lr):
+        n, _, H, W = x.shape
+        loss = C.c_double(0.0)
+        check_cnn(nat.lib.tnlm_cnn_train_step(self._n, self._chk(x, "x"), self._chk(t, "t"), n, H, W, float(lr),
+                                              C.byref(loss)))
+        return loss.value
+
+    def save(self, path):
+        """Full training checkpoint (parameters, Adam moments, step)."""
+        check_cnn(nat.lib.tnlm_cnn_save(self._n, str(path).encode()))
+
+    def save_weights(self, path):
+        """Inference weights: convolution weights as BF16 bit patterns (the
+        precision the network computes with) and biases as FP32, in an .npz."""
+        p = self.get_params()
+        nw = self._num_weights()
+        bits = p[:nw].view(np.uint32)
+        w16 = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.uint16)
+        np.savez(path, w_bf16=w16, bias=p[nw:], meta=np.array([self.phases, self.base], np.int64),
+                 scale=np.array([self.scale], np.float32))
+
+    def load_weights(self, path):
+        z = np.load(path, allow_pickle=False)
+        meta = z["meta"]
+        if int(meta[0]) != self.phases or int(meta[1]) != self.base or abs(float(z["scale"][0]) - self.scale) > 0:
+            raise ValueError("weights are for a different network shape or input scale")
+        w = (z["w_bf16"].astype(np.uint32) << 16).view(np.float32)
+        self.set_params(np.concatenate([w, z["bias"].astype(np.float32)]))
+
+    def _num_weights(self) -> int:
+        b, P = self.base, self.phases
+        chans = [(P, b, 3), (b, b, 3), (b, 2 * b, 3), (2 * b, 2 * b, 3), (2 * b, 4 * b, 3), (4 * b, 4 * b, 3),
+                 (4 * b, 8 * b, 3), (8 * b, 8 * b, 3), (12 * b, 4 * b, 3), (4 * b, 4 * b, 3), (6 * b, 2 * b, 3),
+                 (2 * b, 2 * b, 3), (3 * b, b, 3), (b, b, 3), (b, P, 1)]
+        return sum(ci * co * k * k for ci, co, k in chans)
+
+    def load(self, path):
+        check_cnn(nat.lib.tnlm_cnn_load(self._n, str(path).encode()))
+
+
+def data_cost(recon, y, w, f) -> float:
+    out = C.c_double(0.0)
+    check(nat.lib.tnlm_data_cost(recon._ctx, recon._sino(y, "y"), recon._sino(w, "w"), recon._img(f, "f"),
+                                 C.byref(out)))
+    return out.value
+
+
+def warm_starts(recons, ys, ws, net, batch=4):
+    """f^(0) for each slice (list of Recon contexts of the slices' geometries):
+    network estimate from the per-phase FBPs, or the FBP of all phases when
+    the fallback rule rejects it. Returns (images, used_warm flags)."""
+    fbps = [rc.fbp(y, all_phases=False) for rc, y in zip(recons, ys)]
+    outs = [None] * len(recons)
+    # group slices of equal shape for batched inference
+    order = sorted(range(len(recons)), key=lambda k: (recons[k].L,))
+    for start in range(0, len(order), batch):
+        grp = [k for k in order[start:start + batch] if recons[k].L == recons[order[start]].L]
+        rest = [k for k in order[start:start + batch] if k not in grp]
+        for g in (grp, rest):
+            if not g:
+                continue
+            x = torch.stack([fbps[k] for k in g])
+            o = net.forward(x)
+            for j, k in enumerate(g):
+                outs[k] = o[j].contiguous()
+    f0s, used = [], []
+    for rc, y, w, o in zip(recons, ys, ws, outs):
+        ok = bool(torch.isfinite(o).all().item())
+        cold = rc.fbp(y, all_phases=True)
+        if ok and data_cost(rc, y, w, o) <= data_cost(rc, y, w, cold):
+            f0s.append(o)
+            used.append(True)
+        else:
+            f0s.append(cold)
+            used.append(False)
+    return f0s, used
+
+
+def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, window=15, log=None):
+    """Training pairs produced by the method: (per-phase FBP, TNLM solved to tol).
+    Returns (inputs [n][N][L][L], targets [n][N][L][L]) on the device, plus iterations."""
+    from .recon import Batch, Recon
+    xs, ts, its = [], [], []
+    for s0 in range(0, len(cases), chunk):
+        cs = cases[s0:s0 + chunk]
+        ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(device) for c in cs]
+        wts = [torch.from_numpy(np.asarray(c.w, np.float32)).to(device) for c in cs]
+        bt = Batch([c.geom for c in cs], patch=patch, window=window, h=cs[0].h, mu_hat=cs[0].mu_hat,
+                   max_outer=max_outer, tol=tol, device=device)
+        fs, iters, rel, sts, st = bt.solve(ys, wts)
+        its += iters
+        for c, y, f in zip(cs, ys, fs):
+            rc = Recon.from_geometry(c.geom, patch=patch, window=window, h=c.h, mu_hat=c.mu_hat, device=device)
+            xs.append(rc.fbp(y, all_phases=False))
+            ts.append(f)
+        bt.close()
+        if log:
+            log(f"pairs {min(s0 + chunk, len(cases))}/{len(cases)} (iterations {min(iters)}..{max(iters)})")
+    return torch.stack(xs), torch.stack(ts), its
+
+
+def train(net, X, T, *, epochs=4, batch=8, lr=1e-3, lr_final=1e-4, seed=0, log=None, time_limit_s=None):
+    """Adam on the MSE of the network output against the targets; returns the loss history."""
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    steps = epochs * max(1, n // batch)
+    hist = []
+    t0 = time.time()
+    k = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        for b0 in range(0, n - batch + 1, batch):
+            idx = torch.as_tensor(perm[b0:b0 + batch], device=X.device)
+            frac = k / max(1, steps - 1)
+            cur = lr * (lr_final / lr) ** frac
+            loss = net.train_step(X.index_select(0, idx).contiguous(), T.index_select(0, idx).contiguous(), cur)
+            hist.append(loss)
+            k += 1
+            if time_limit_s is not None and time.time() - t0 > time_limit_s:
+                break
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mean loss {np.mean(hist[-max(1, n // batch):]):.4e} ({time.time() - t0:.0f} s)")
+        if time_limit_s is not None and time.time() - t0 > time_limit_s:
+            break
+    return hist
+
+
+__all__ = ["WarmStartNet", "warm_starts", "make_pairs", "train", "data_cost"]

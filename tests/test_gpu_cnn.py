@@ -1,0 +1,133 @@
+"""Warm-start network kernels against the FP64 CPU reference network, training,
+checkpointing, and the warm-start pipeline on small slices."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import announce, recon_for, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def net(P=10, b=32, seed=3):
+    from paper_1009_1351_amd.warmstart import WarmStartNet
+    return WarmStartNet(phases=P, base=b, seed=seed)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("P,b,H,n", [(10, 32, 16, 2), (3, 8, 24, 1)])
+def test_gradients_match_fp64_reference(P, b, H, n):
+    from oracle import cnn_ref
+    nt = net(P, b)
+    params = nt.get_params().astype(np.float64)
+    # give the head non-trivial weights so every layer receives gradient
+    rng = np.random.default_rng(7)
+    ws, bs = cnn_ref.unpack(params.copy(), P, b)
+    off = sum(co * ci * k * k for ci, co, k, _ in cnn_ref.layers(P, b)[:-1])
+    params[off:off + ws[-1].size] = rng.standard_normal(ws[-1].size) * 0.2
+    params[-(sum(co for _, co, _, _ in cnn_ref.layers(P, b))):] = rng.standard_normal(
+        sum(co for _, co, _, _ in cnn_ref.layers(P, b))) * 0.02
+    nt.set_params(params.astype(np.float32))
+    x = rng.uniform(0.0, 0.03, size=(n, P, H, H)).astype(np.float32)
+    t = (x + rng.normal(0, 0.002, size=x.shape)).astype(np.float32)
+    loss, g = nt.loss_grad(to_dev(x).reshape(n, P, H, H), to_dev(t).reshape(n, P, H, H))
+    p32 = params.astype(np.float32).astype(np.float64)
+    lref, gref = cnn_ref.loss_and_grad(p32, x.astype(np.float64), t.astype(np.float64), P, b, 50.0,
+                                       bf16_storage=True)
+    announce(f"cnn P={P} b={b}: loss gpu {loss:.6e} ref {lref:.6e}")
+    assert abs(loss - lref) <= 2e-3 * lref
+    offw = 0
+    errs = []
+    for li, (ci, co, k, _) in enumerate(cnn_ref.layers(P, b)):
+        m = co * ci * k * k
+        e = rel(g[offw:offw + m].astype(np.float64), gref[offw:offw + m])
+        errs.append(e)
+        offw += m
+    announce("weight-gradient rel L2 per layer: " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) < 1e-3
+    nb = sum(co for _, co, _, _ in cnn_ref.layers(P, b))
+    assert rel(g[-nb:].astype(np.float64), gref[-nb:]) < 1e-3
+
+
+def test_first_adam_step_matches_closed_form():
+    # at step 1 the bias-corrected moments are g and g^2, so Adam moves each
+    # parameter by lr * g / (|g| + eps)
+    P, H, n, lr = 10, 16, 2, 1e-3
+    nt = net(P, 32, seed=4)
+    rng = np.random.default_rng(8)
+    x = to_dev(rng.uniform(0.0, 0.03, size=(n, P, H, H))).reshape(n, P, H, H)
+    t = 0.5 * x + 0.005
+    p0 = nt.get_params().astype(np.float64)
+    _, g = nt.loss_grad(x, t)
+    nt.train_step(x, t, lr)
+    p1 = nt.get_params().astype(np.float64)
+    g = g.astype(np.float64)
+    want = p0 - lr * g / (np.abs(g) + 1e-8)
+    err = np.abs(p1 - want)
+    announce(f"adam step 1: max |p1 - closed form| = {err.max():.2e}, moved {np.count_nonzero(p1 != p0)} of {p0.size}")
+    assert np.all(err <= 1e-4 * lr + 4 * np.spacing(np.abs(p0).astype(np.float32)).astype(np.float64))
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(tmp_path):
+    P, H, n = 10, 32, 4
+    nt = net(P, 32, seed=11)
+    rng = np.random.default_rng(5)
+    x = to_dev(rng.uniform(0.0, 0.03, size=(n, P, H, H))).reshape(n, P, H, H)
+    t = 0.5 * x + 0.005   # a learnable map of the input
+    hist = [nt.train_step(x, t, 2e-3) for _ in range(200)]
+    announce("overfit: loss " + " ".join(f"{hist[k]:.3e}" for k in (0, 25, 50, 100, 150, 199)))
+    assert np.mean(hist[-10:]) < 0.5 * np.mean(hist[:10])
+    p = tmp_path / "net.ckpt"
+    nt.save(p)
+    y1 = nt.forward(x)
+    nt2 = net(P, 32, seed=99)
+    nt2.load(p)
+    assert torch.equal(nt2.forward(x), y1)
+    # training continues identically from the checkpoint (Adam moments and step restored)
+    a = nt.train_step(x, t, 1e-3)
+    b = nt2.train_step(x, t, 1e-3)
+    assert a == b and torch.equal(nt.forward(x), nt2.forward(x))
+
+
+def test_corrupted_checkpoint_is_rejected(tmp_path):
+    from paper_1009_1351_amd import TnlmError
+    nt = net(10, 32)
+    p = tmp_path / "bad.ckpt"
+    nt.save(p)
+    raw = bytearray(p.read_bytes())
+    raw[40:48] = b"\xff\xff\xff\x7f\xff\xff\xff\x7f"    # NaN parameters
+    p.write_bytes(bytes(raw))
+    with pytest.raises(TnlmError):
+        nt.load(p)
+    (tmp_path / "short.ckpt").write_bytes(b"TNLMCNN1" + b"\x00" * 10)
+    with pytest.raises(TnlmError):
+        nt.load(tmp_path / "short.ckpt")
+
+
+def test_warm_start_pipeline_small():
+    from paper_1009_1351_amd.warmstart import WarmStartNet, make_pairs, train, warm_starts
+    cases = [synth.make_case("C5train", slice_index=s, L=48, V=24, B=64, patch=5, window=9) for s in range(6)]
+    X, T, its = make_pairs(cases, device=torch.device("cuda"), chunk=6, tol=1e-3, max_outer=60, patch=5, window=9)
+    announce(f"pairs: iterations to tol {its}")
+    nt = WarmStartNet(phases=10, base=8, seed=1)
+    hist = train(nt, X, T, epochs=20, batch=2, lr=2e-3)
+    assert hist[-1] < hist[0]
+    recons = [recon_for(c.geom, patch=5, window=9, h=c.h, mu_hat=c.mu_hat, init="user", tol=1e-3, max_outer=60)
+              for c in cases[:2]]
+    ys = [to_dev(c.y) for c in cases[:2]]
+    ws = [to_dev(c.w) for c in cases[:2]]
+    f0s, used = warm_starts(recons, ys, ws, nt)
+    assert all(torch.isfinite(f).all() for f in f0s)
+    for rc, y, w, f0 in zip(recons, ys, ws, f0s):
+        f, k, r, st = rc.solve(y, w, f0.clone())
+        assert st == 0 and r < 1e-3
