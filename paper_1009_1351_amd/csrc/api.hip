@@ -64,8 +64,10 @@ struct Engine {
     Batch batch{};
     SliceDesc *d_sl = nullptr;
     float4 *rt0 = nullptr, *rt1 = nullptr, *vt = nullptr;
+    int4 *vo = nullptr;
     float *hfilt = nullptr, *cw = nullptr;
-    Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{};
+    Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{}, st_tr{};
+    float *fT = nullptr;   // transposed copy of the image a projection reads
     CglsBufs cb{};
     float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
@@ -179,6 +181,7 @@ static tnlm_status validate_geom(const tnlm_geometry *g) {
     const double half_diag = 0.7071067811865476 * g->pixel_mm * g->L;
     if (!(g->sad_mm > half_diag + 2.0 * g->pixel_mm))
         return fail(TNLM_E_INVALID_ARG, "the source circle must enclose the image square (SAD > half-diagonal + 2 pixels)");
+    if (!((g->n_bins - 1) * g->dgamma_rad < M_PI)) return fail(TNLM_E_INVALID_ARG, "the fan must be narrower than pi");
     for (long k = 0; k < (long)g->n_phases * g->n_views; ++k)
         if (!std::isfinite(g->view_angles_rad[k])) return fail(TNLM_E_NONFINITE, "non-finite view angle");
     return TNLM_OK;
@@ -205,8 +208,9 @@ static tnlm_status validate_params(const tnlm_params *p, int minL) {
 }
 
 // Per-ray plane tables in double precision, rounded once to float.
-static void append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
-                          std::vector<float4> &vt, std::vector<float> &hf, std::vector<float> &cw) {
+static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
+                          std::vector<float4> &vt, std::vector<int4> &vo, std::vector<float> &hf,
+                          std::vector<float> &cw) {
     const int N = g.n_phases, V = g.n_views, B = g.n_bins, L = g.L;
     const double D = g.pixel_mm, X0 = -0.5 * D * L;
     for (int i = 0; i < N; ++i)
@@ -225,6 +229,19 @@ static void append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std:
                                           (float)((X0 - oy) * iy)));
                 rt1.push_back(make_float4((float)ox, (float)oy, (float)ux, (float)uy));
             }
+            // orientation of the view's rays: the sign of Ax (and Ay) is that of
+            // bin 0 below bin bx (by) and the opposite from there on; the fan is
+            // narrower than pi, so each sign changes at most once across it
+            const float4 *r = rt0.data() + rt0.size() - B;
+            const bool x0 = r[0].x > 0.0f, y0 = r[0].z > 0.0f;
+            int bx = B, by = B;
+            for (int b = B - 1; b >= 0; --b) {
+                if ((r[b].x > 0.0f) != x0) bx = b;
+                if ((r[b].z > 0.0f) != y0) by = b;
+            }
+            for (int b = 0; b < B; ++b)   // the back-projector relies on a single change
+                if (((r[b].x > 0.0f) != x0) != (b >= bx) || ((r[b].z > 0.0f) != y0) != (b >= by)) return false;
+            vo.push_back(make_int4(bx, by, (x0 ? 1 : 0) | (y0 ? 2 : 0), 0));
         }
     const double a = g.dgamma_rad;
     for (int m = -(B - 1); m <= B - 1; ++m) {
@@ -239,15 +256,36 @@ static void append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std:
     }
     for (int b = 0; b < B; ++b)
         cw.push_back((float)(g.sad_mm * std::cos(((double)b - 0.5 * (B - 1) + g.det_offset_bins) * a)));
+    return true;
 }
 
-static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &counts, int cap) {
-    std::vector<int> pre(counts.size() + 1, 0);
-    for (size_t s = 0; s < counts.size(); ++s) pre[s + 1] = pre[s] + counts[s];
-    int *d = nullptr;
+// Work items of a stage: counts[s] items of slice s, each of estimated cost
+// cost[s] (empty: all equal). Besides the prefix table, the item boundaries
+// of the 8 XCD ranges are cut at equal cumulative cost.
+static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &counts, int cap,
+                              const std::vector<double> &cost = {}) {
+    const size_t ns = counts.size();
+    std::vector<int> pre(ns + 1, 0);
+    for (size_t s = 0; s < ns; ++s) pre[s + 1] = pre[s] + counts[s];
+    std::vector<double> cpre(ns + 1, 0.0);
+    for (size_t s = 0; s < ns; ++s) cpre[s + 1] = cpre[s] + counts[s] * (cost.empty() ? 1.0 : cost[s]);
+    std::vector<int> xb(9, 0);
+    for (int x = 1; x < 8; ++x) {
+        const double target = cpre[ns] * x / 8.0;
+        size_t s = 0;
+        while (s + 1 < ns && cpre[s + 1] < target) ++s;
+        const double c = cost.empty() ? 1.0 : cost[s];
+        const double k = c > 0.0 ? std::ceil((target - cpre[s]) / c) : 0.0;
+        xb[x] = std::max(xb[x - 1], std::min(pre[s] + (int)std::max(0.0, k), pre[s + 1]));
+    }
+    xb[8] = pre[ns];
+    int *d = nullptr, *dx = nullptr;
     HIP_TRY(E.alloc(&d, pre.size()));
     HIP_TRY(hipMemcpy(d, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(E.alloc(&dx, xb.size()));
+    HIP_TRY(hipMemcpy(dx, xb.data(), xb.size() * sizeof(int), hipMemcpyHostToDevice));
     st.pre = d;
+    st.xb = dx;
     st.total = pre.back();
     int g = std::min(st.total, cap);
     if (g >= 8) g -= g % 8;
@@ -280,6 +318,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     E.use_graph = !(env_graph && env_graph[0] == '1');
 
     std::vector<float4> rt0, rt1, vt;
+    std::vector<int4> vo;
     std::vector<float> hf, cw;
     E.geoms.assign(geoms, geoms + ns);
     E.angles.resize(ns);
@@ -305,7 +344,8 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         d.sino0 = sino;
         d.hf0 = (int)hf.size();
         d.cw0 = (int)cw.size();
-        append_tables(E.geoms[s], rt0, rt1, vt, hf, cw);
+        if (!append_tables(E.geoms[s], rt0, rt1, vt, vo, hf, cw))
+            return fail(TNLM_E_INVALID_ARG, "ray directions change sign more than once across the fan");
         d.nbp = bp_blocks(d) / d.N;
         d.npp = proj_blocks(d) / d.N;
         d.nrb = params->ssd_mode == TNLM_SSD_BF16_MFMA ? reg_mfma_blocks(d)
@@ -330,11 +370,13 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     HIP_TRY(E.alloc(&E.rt0, rt0.size()));
     HIP_TRY(E.alloc(&E.rt1, rt1.size()));
     HIP_TRY(E.alloc(&E.vt, vt.size()));
+    HIP_TRY(E.alloc(&E.vo, vo.size()));
     HIP_TRY(E.alloc(&E.hfilt, hf.size()));
     HIP_TRY(E.alloc(&E.cw, cw.size()));
     HIP_TRY(hipMemcpy(E.rt0, rt0.data(), rt0.size() * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.rt1, rt1.data(), rt1.size() * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.vt, vt.data(), vt.size() * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(E.vo, vo.data(), vo.size() * sizeof(int4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.hfilt, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.cw, cw.data(), cw.size() * sizeof(float), hipMemcpyHostToDevice));
     E.batch.ns = ns;
@@ -342,25 +384,36 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     E.batch.rt0 = E.rt0;
     E.batch.rt1 = E.rt1;
     E.batch.vt = E.vt;
+    E.batch.vo = E.vo;
     E.batch.skip = nullptr;
 
-    std::vector<int> cfp, cbp, cvec, creg, cff, cfa, cfph;
+    std::vector<int> cfp, cbp, cvec, creg, cff, cfa, cfph, ctr;
+    std::vector<double> kfp, kbp;
     for (auto &d : E.sl) {
         cfp.push_back(proj_blocks(d));
         cbp.push_back(bp_blocks(d));
+        ctr.push_back(tr_blocks(d));
+        // cost models: a projector block walks 256 rays of ~1.2 L cells; a
+        // back-projector tile runs V views of a ~40-operation set-up plus
+        // ~14 operations per candidate bin, ~1.5 + B D / (fan * SAD) bins
+        kfp.push_back((double)d.L);
+        const double cand = 1.5 + d.B * (double)d.D / (d.B * (double)d.dgamma * 541.0);
+        kbp.push_back(d.V * (40.0 + 14.0 * cand));
         cvec.push_back(d.N * vec_blocks(d));
         creg.push_back(d.nrb);
         cff.push_back(d.N * d.V);
         cfa.push_back(fbp_bp_blocks(d, 1));
         cfph.push_back(fbp_bp_blocks(d, 0));
     }
-    if ((st = make_stage(E, E.st_fp, cfp, kCUs * 8)) != TNLM_OK) return st;
-    if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_fp, cfp, kCUs * 8, kfp)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8, kbp)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_vec, cvec, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_reg, creg, kCUs * 4)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_ffilt, cff, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_fbp_all, cfa, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_fbp_ph, cfph, kCUs * 8)) != TNLM_OK) return st;
+    if ((st = make_stage(E, E.st_tr, ctr, kCUs * 8)) != TNLM_OK) return st;
+    HIP_TRY(E.alloc(&E.fT, E.nimg));
 
     CglsBufs &b = E.cb;
     HIP_TRY(E.alloc(&b.u, E.nimg));
@@ -399,17 +452,22 @@ static void enqueue_data_step(Engine *E, const Batch &bt, const float *y, const 
     hipStream_t st = E->cur;
     const int M1 = E->prm.m1_cgls;
     if (M1 == 0) {
-        TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_PLAIN, f, nullptr, nullptr, b.q, nullptr, nullptr, st));
+        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, f, E->fT, st));
+        TIMED(E, K_PROJECT,
+              launch_project(bt, E->st_fp, PROJ_PLAIN, f, E->fT, nullptr, nullptr, b.q, nullptr, nullptr, st));
         TIMED(E, K_VECTOR, launch_weighted_resid(bt, E->st_vec, b.q, y, w, E->Q, st));
         TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, E->Q, b.t, nullptr, st));
         TIMED(E, K_VECTOR, launch_gradient_step(bt, E->st_vec, f, b.t, 1.0f / E->prm.beta, b.u, st));
         return;
     }
     TIMED(E, K_VECTOR, launch_copy_skip(bt, E->st_vec, true, f, b.u, st));
-    TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_RESID, b.u, y, b.sw, b.r, b.rw, nullptr, st));
+    TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.u, E->fT, st));
+    TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_RESID, b.u, E->fT, y, b.sw, b.r, b.rw, nullptr, st));
     TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.s, b.gpart[0], st));
     for (int m = 0; m < M1; ++m) {
-        TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_SCALED, b.s, nullptr, b.sw, b.q, nullptr, b.qpart, st));
+        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.s, E->fT, st));
+        TIMED(E, K_PROJECT,
+              launch_project(bt, E->st_fp, PROJ_SCALED, b.s, E->fT, nullptr, b.sw, b.q, nullptr, b.qpart, st));
         TIMED(E, K_VECTOR, launch_cgls_update(bt, E->st_vec, b, m, m & 1, st));
         if (m + 1 < M1) {
             TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.t, b.gpart[(m + 1) & 1], st));
@@ -594,12 +652,13 @@ static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
     }
     float *g = nullptr, *o4 = nullptr, *o8 = nullptr;
     SliceDesc *dd = nullptr;
-    int *pre = nullptr;
+    int *pre = nullptr, *xbd = nullptr;
     HIP_TRY(hipMalloc(&g, h.size() * sizeof(float)));
     HIP_TRY(hipMalloc(&o4, h.size() * sizeof(float)));
     HIP_TRY(hipMalloc(&o8, h.size() * sizeof(float)));
     HIP_TRY(hipMalloc(&dd, 2 * sizeof(SliceDesc)));
     HIP_TRY(hipMalloc(&pre, 4 * sizeof(int)));
+    HIP_TRY(hipMalloc(&xbd, 18 * sizeof(int)));
     HIP_TRY(hipMemcpy(g, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
     float ms[2] = {0, 0};
     const int cand[2] = {8, 4};
@@ -616,7 +675,10 @@ static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
         bt.ns = 1;
         bt.sl = dd + c;
         bt.skip = nullptr;
-        Stage sg{pre + 2 * c, d.nrb, std::max(1, std::min(d.nrb, kCUs * 4))};
+        int xb[9];
+        for (int x = 0; x <= 8; ++x) xb[x] = (int)((long long)d.nrb * x / 8);
+        HIP_TRY(hipMemcpy(xbd + 9 * c, xb, sizeof(xb), hipMemcpyHostToDevice));
+        Stage sg{pre + 2 * c, xbd + 9 * c, d.nrb, std::max(1, std::min(d.nrb, kCUs * 4))};
         if (sg.grid >= 8) sg.grid -= sg.grid % 8;
         float *o = c == 0 ? o8 : o4;
         hipEvent_t a, b;
@@ -639,6 +701,7 @@ static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
     (void)hipFree(o8);
     (void)hipFree(dd);
     (void)hipFree(pre);
+    (void)hipFree(xbd);
     const bool same = std::memcmp(out[0].data(), out[1].data(), out[0].size() * sizeof(float)) == 0;
     const int pick = (same && ms[1] < ms[0]) ? 4 : 8;
     if (chosen) *chosen = pick;
@@ -740,8 +803,9 @@ extern "C" tnlm_status tnlm_project(tnlm_ctx *ctx, const float *d_f, float *d_q)
     if (!d_f || !d_q) return fail(TNLM_E_INVALID_ARG, "null device pointer");
     Engine *E = &ctx->e;
     E->cur = E->stream;
-    TIMED(E, K_PROJECT,
-          launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, nullptr, nullptr, d_q, nullptr, nullptr, E->stream));
+    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fT, E->stream));
+    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, E->fT, nullptr, nullptr, d_q, nullptr,
+                                       nullptr, E->stream));
     return last_launch();
 }
 
@@ -803,8 +867,9 @@ extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const flo
     if (!d_y || !d_w || !d_f || !out) return fail(TNLM_E_INVALID_ARG, "null pointer");
     Engine *E = &ctx->e;
     E->cur = E->stream;
-    TIMED(E, K_PROJECT,
-          launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, nullptr, nullptr, E->cb.q, nullptr, nullptr, E->stream));
+    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fT, E->stream));
+    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, E->fT, nullptr, nullptr, E->cb.q,
+                                       nullptr, nullptr, E->stream));
     const int nb = launch_wsq_sum(E->cb.q, d_y, d_w, E->nsino, E->cost_part, E->stream);
     std::vector<double> part(nb);
     HIP_TRY(hipMemcpyAsync(part.data(), E->cost_part, nb * sizeof(double), hipMemcpyDeviceToHost, E->stream));

@@ -32,4 +32,15 @@ __device__ inline double block_sum_array(const double *partials, int n, double *
 
 __device__ inline bool skip_now(const int *skip) { return skip != nullptr && *skip != 0; }
 
+// Values the caller knows to be equal in every lane of the wave (block
+// indices, slice descriptors), moved to scalar registers.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ const float *wave_uniform(const float *p) {
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (const float *)(((unsigned long long)hi << 32) | lo);
+}
+
 }  // namespace tnlm

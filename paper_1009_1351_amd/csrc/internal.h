@@ -36,6 +36,7 @@ struct SliceDesc {
 // Per-stage block prefix: blocks of slice s are [pre[s], pre[s+1]).
 struct Stage {
     const int *pre;   // device [ns + 1]
+    const int *xb;    // device [9]: work items [xb[x], xb[x+1]) go to XCD x
     int total;        // pre[ns]
     int grid;         // persistent grid size
 };
@@ -46,6 +47,7 @@ struct Batch {
     const float4 *rt0 = nullptr;     // rays: (Ax, Bx, Ay, By), T_x(k) = fma(k, Ax, Bx)
     const float4 *rt1 = nullptr;     // rays: (ox, oy, ux, uy)
     const float4 *vt = nullptr;      // views: (sx, sy, cos th, sin th)
+    const int4 *vo = nullptr;        // views: (bx, by, flags, 0), sign changes of Ax / Ay over the bins
     const int *skip = nullptr;       // device [ns] per-slice stop flags (nullable: run all)
 };
 
@@ -54,45 +56,64 @@ struct RegParams {
     float h, mu_hat;
 };
 
+// Tables the host fills at set-up (stage prefixes, slice descriptors, view
+// tables) are never written by a kernel. Read through the constant address
+// space, a wave-uniform index loads them with scalar loads into scalar
+// registers.
+template <class T>
+__device__ __forceinline__ T load_const(const T *p, long long i) {
+    static_assert(sizeof(T) % 4 == 0, "tables are made of 4-byte words");
+    using cword = const __attribute__((address_space(4))) int;
+    cword *src = (cword *)(p + i);
+    T out;
+    int *dst = reinterpret_cast<int *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return out;
+}
+
 // Block index -> (slice, local block). Block-uniform.
 __device__ __forceinline__ int find_slice(const int *pre, int ns, int gb) {
     int lo = 0, hi = ns - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= gb) lo = mid;
+        if (load_const(pre, mid) <= gb) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
 // Persistent loop order: the 8 XCDs receive consecutive hardware block ids in
-// turn; give each XCD a contiguous range of work items so that the blocks
-// sharing an XCD (and its L2) work on the same slices and phases.
-__device__ __forceinline__ void xcd_range(int total, int &first, int &stride, int &count) {
+// turn; each XCD gets a contiguous range of work items, so that the blocks
+// sharing an XCD (and its L2) work on the same slices and phases. The ranges
+// are cut on the host to equal estimated cost (slices of a batch differ in
+// size and view count), not to equal item counts.
+__device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stride, int &count) {
     const int nx = 8;
     const int g = (int)gridDim.x;
     if (g < nx) {   // fewer blocks than XCDs: plain grid-stride order
         first = (int)blockIdx.x;
         stride = g;
-        count = total;
+        count = st.total;
         return;
     }
     const int x = (int)blockIdx.x % nx;
     const int per_x = (g - x + nx - 1) / nx;          // blocks on this XCD
     const int k = (int)blockIdx.x / nx;                // rank within the XCD
-    const int chunk = (total + nx - 1) / nx;
-    const int lo = std::min(total, x * chunk), hi = std::min(total, lo + chunk);
-    first = lo + k;
+    first = load_const(st.xb, x) + k;
     stride = per_x;
-    count = hi;
+    count = load_const(st.xb, x + 1);
 }
 
 // ---- projector (proj.hip)
 enum ProjMode { PROJ_PLAIN = 0, PROJ_RESID = 1, PROJ_SCALED = 2 };
 int proj_blocks(const SliceDesc &s);
 int bp_blocks(const SliceDesc &s);
-void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *y, const float *sw,
-                    float *out, float *out2, double *partials, hipStream_t strm);
+int tr_blocks(const SliceDesc &s);
+// fT: the same image stack transposed per phase (launch_transpose)
+void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fT, hipStream_t strm);
+void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *fT, const float *y,
+                    const float *sw, float *out, float *out2, double *partials, hipStream_t strm);
 void launch_backproject(const Batch &b, const Stage &st, const float *q, float *f, double *partials,
                         hipStream_t strm);
 

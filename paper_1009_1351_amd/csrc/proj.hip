@@ -27,15 +27,27 @@ constexpr int kRaysPerBlock = kBlock;
 
 int proj_blocks(const SliceDesc &s) { return s.N * s.V * ((s.B + kRaysPerBlock - 1) / kRaysPerBlock); }
 
-// One ray: Siddon walk of image fi (L x L) along plane table A and ray point/direction O.
-__device__ __forceinline__ float walk_ray(const float4 A, const float4 O, const float *__restrict__ fi, int L,
+// Image reads of the walk go through a buffer resource spanning one phase
+// image: an offset outside it reads 0 without a memory access (the walk
+// prefetches the cell after the current one, which lies outside the image
+// once the ray leaves it).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float *fi, int L) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(fi), (short)0, L * L * 4, 0x00020000);
+}
+
+__device__ __forceinline__ float image_at(__amdgpu_buffer_rsrc_t img, int byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, byte_off, 0, 0));
+}
+
+// One ray: Siddon walk of one phase image (L x L) along plane table A and
+// ray point/direction O.
+__device__ __forceinline__ float walk_ray(const float4 A, const float4 O, __amdgpu_buffer_rsrc_t img, int L,
                                           float X0, float invD) {
     const float tx0 = plane_t(0, A.x, A.y), txL = plane_t(L, A.x, A.y);
     const float ty0 = plane_t(0, A.z, A.w), tyL = plane_t(L, A.z, A.w);
     const float tin = fmaxf(fminf(tx0, txL), fminf(ty0, tyL));
     const float tout = fminf(fmaxf(tx0, txL), fmaxf(ty0, tyL));
-    float acc = 0.0f;
-    if (!(tout > tin)) return acc;
+    if (!(tout > tin)) return 0.0f;
     const int dc = A.x > 0.0f ? 1 : -1, dr = A.z > 0.0f ? 1 : -1;
     const int hc = dc > 0 ? 1 : 0, hr = dr > 0 ? 1 : 0;   // hi plane of cell c = c + hc
     // first cell: estimate from the entry point, then settle it on the plane
@@ -52,42 +64,98 @@ __device__ __forceinline__ float walk_ray(const float4 A, const float4 O, const 
     }
     // Walk: tcur is the lo plane of the current cell (max of its x/y lo
     // planes); the next crossing is min(txh, tyh). Each segment equals the
-    // clip of the cell computed by the transpose kernel, bit for bit.
+    // clip of the cell computed by the transpose kernel, bit for bit. One
+    // grid line is crossed per pass, x first on a tie (the cell entered then
+    // has a zero-length segment, as its clip has). T is monotone in k and the
+    // exit planes' values bound tout, so tn reaches tout after at most L + 1
+    // x-steps and L + 1 y-steps: the loop ends within 2L + 3 passes.
     float fkx = (float)(c + hc), fky = (float)(r + hr);
     float txh = plane_t(c + hc, A.x, A.y), tyh = plane_t(r + hr, A.z, A.w);
     float tcur = fmaxf(plane_t(c + 1 - hc, A.x, A.y), plane_t(r + 1 - hr, A.z, A.w));
     const float dcf = (float)dc, drf = (float)dr;
-    const int sx_ofs = dc, sy_ofs = dr * L;
-    int idx = r * L + c;
-    // every step moves past at least one grid line: at most 2L + 1 cells
-    for (int it = 0; it < 2 * L + 2; ++it) {
-        const float tn = fminf(txh, tyh);
-        acc = fmaf(tn - tcur, fi[idx], acc);
+    const int ox = 4 * dc, oy = 4 * dr * L;
+    int off = 4 * (r * L + c);
+    float val = image_at(img, off);
+    float acc = 0.0f;
+    for (;;) {
+        const bool sx = txh <= tyh;
+        const float tn = fminf(fminf(txh, tyh), tout);
+        off += sx ? ox : oy;
+        fkx += sx ? dcf : 0.0f;
+        fky += sx ? 0.0f : drf;
+        const float nval = image_at(img, off);   // next cell, in flight during this one
+        acc = fmaf(tn - tcur, val, acc);
         if (!(tn < tout)) break;   // the cell just added was the last one
         tcur = tn;
-        const bool sx = txh <= tyh, sy = tyh <= txh;
-        fkx += sx ? dcf : 0.0f;
-        fky += sy ? drf : 0.0f;
-        idx += (sx ? sx_ofs : 0) + (sy ? sy_ofs : 0);
-        if ((unsigned)idx >= (unsigned)(L * L)) break;   // memory guard; never taken
-        txh = sx ? fmaf(fkx, A.x, A.y) : txh;
-        tyh = sy ? fmaf(fky, A.z, A.w) : tyh;
+        val = nval;
+        txh = fmaf(fkx, A.x, A.y);
+        tyh = fmaf(fky, A.z, A.w);
     }
     return acc;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const float *__restrict__ f,
-                                                    const float *__restrict__ y, const float *__restrict__ sw,
-                                                    float *__restrict__ out, float *__restrict__ out2,
-                                                    double *__restrict__ partials) {
-    __shared__ double sh[kBlock];
+// Image stacks are row-major, (r, c) at r L + c. Lanes of a projector wave
+// are neighbouring rays: for a view whose rays run mostly along y they sit in
+// one row at neighbouring columns (few cache lines per load), for a view
+// whose rays run mostly along x they sit in neighbouring rows (one line per
+// lane). The latter views walk a transposed copy, (r, c) at c L + r, with
+// the roles of the axes exchanged; the walk computes the same segments (a
+// tie now steps the other axis first, through a cell of zero length), so the
+// sum is bitwise the same for a finite image.
+constexpr int kTr = 32;
+
+int tr_blocks(const SliceDesc &s) {
+    const int t = (s.L + kTr - 1) / kTr;
+    return s.N * t * t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_transpose(Batch bt, Stage st, const float *__restrict__ f,
+                                                      float *__restrict__ fT) {
+    __shared__ float tile[kTr][kTr + 1];
     int first, stride, count;
-    xcd_range(st.total, first, stride, count);
+    xcd_range(st, first, stride, count);
+    const int tx = threadIdx.x % kTr, ty = threadIdx.x / kTr;   // 32 x 8
     for (int gb = first; gb < count; gb += stride) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
-        const SliceDesc sd = bt.sl[s];
+        const SliceDesc sd = load_const(bt.sl, s);
+        const int L = sd.L, t = (L + kTr - 1) / kTr;
+        int lb = gb - load_const(st.pre, s);
+        const int bx = lb % t;
+        lb /= t;
+        const int by = lb % t, i = lb / t;
+        const float *__restrict__ src = f + sd.img0 + (long long)i * L * L;
+        float *__restrict__ dst = fT + sd.img0 + (long long)i * L * L;
+        for (int k = 0; k < kTr; k += kBlock / kTr) {
+            const int r = by * kTr + ty + k, c = bx * kTr + tx;
+            if (r < L && c < L) tile[ty + k][tx] = src[r * L + c];
+        }
+        __syncthreads();
+        for (int k = 0; k < kTr; k += kBlock / kTr) {
+            const int c = bx * kTr + ty + k, r = by * kTr + tx;
+            if (r < L && c < L) dst[c * L + r] = tile[tx][ty + k];
+        }
+        __syncthreads();
+    }
+}
+
+void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fT, hipStream_t strm) {
+    if (st.total == 0) return;
+    k_transpose<<<st.grid, kBlock, 0, strm>>>(b, st, f, fT);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const float *__restrict__ f,
+                                                    const float *__restrict__ fT, const float *__restrict__ y,
+                                                    const float *__restrict__ sw, float *__restrict__ out,
+                                                    float *__restrict__ out2, double *__restrict__ partials) {
+    __shared__ double sh[kBlock];
+    int first, stride, count;
+    xcd_range(st, first, stride, count);
+    for (int gb = first; gb < count; gb += stride) {
+        const int s = find_slice(st.pre, bt.ns, gb);
+        if (bt.skip && bt.skip[s]) continue;
+        const SliceDesc sd = load_const(bt.sl, s);
         const int nbx = (sd.B + kRaysPerBlock - 1) / kRaysPerBlock;
         int lb = gb - st.pre[s];
         const int bx = lb % nbx;
@@ -95,10 +163,19 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
         const int v = lb % sd.V, i = lb / sd.V;
         const int b = bx * kRaysPerBlock + threadIdx.x;
         const long long ray = ((long long)i * sd.V + v) * sd.B + b;   // within the slice
+        const int L = sd.L;
+        const float4 vs = load_const(bt.vt, sd.view0 + (long long)i * sd.V + v);   // cos th, sin th in z, w
+        const bool tr = fabsf(vs.z) > fabsf(vs.w);   // central ray mostly along x
+        const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.img0 + (long long)i * L * L, L);
         float acc = 0.0f;
-        if (b < sd.B)
-            acc = walk_ray(bt.rt0[sd.ray0 + ray], bt.rt1[sd.ray0 + ray], f + sd.img0 + (long long)i * sd.L * sd.L,
-                           sd.L, sd.X0, 1.0f / sd.D);
+        if (b < sd.B) {
+            float4 A = bt.rt0[sd.ray0 + ray], O = bt.rt1[sd.ray0 + ray];
+            if (tr) {
+                A = make_float4(A.z, A.w, A.x, A.y);
+                O = make_float4(O.y, O.x, O.w, O.z);
+            }
+            acc = walk_ray(A, O, img, L, sd.X0, 1.0f / sd.D);
+        }
         double part = 0.0;
         if (b < sd.B) {
             const long long e = sd.sino0 + ray;
@@ -122,15 +199,15 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
     }
 }
 
-void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *y, const float *sw,
-                    float *out, float *out2, double *partials, hipStream_t strm) {
+void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *fT, const float *y,
+                    const float *sw, float *out, float *out2, double *partials, hipStream_t strm) {
     if (st.total == 0) return;
     if (mode == PROJ_PLAIN)
-        k_project<PROJ_PLAIN><<<st.grid, kBlock, 0, strm>>>(b, st, f, y, sw, out, out2, partials);
+        k_project<PROJ_PLAIN><<<st.grid, kBlock, 0, strm>>>(b, st, f, fT, y, sw, out, out2, partials);
     else if (mode == PROJ_RESID)
-        k_project<PROJ_RESID><<<st.grid, kBlock, 0, strm>>>(b, st, f, y, sw, out, out2, partials);
+        k_project<PROJ_RESID><<<st.grid, kBlock, 0, strm>>>(b, st, f, fT, y, sw, out, out2, partials);
     else
-        k_project<PROJ_SCALED><<<st.grid, kBlock, 0, strm>>>(b, st, f, y, sw, out, out2, partials);
+        k_project<PROJ_SCALED><<<st.grid, kBlock, 0, strm>>>(b, st, f, fT, y, sw, out, out2, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,12 +239,12 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
                                                         float *__restrict__ fout, double *__restrict__ partials) {
     __shared__ double sh[kBlock];
     int first, stride, count;
-    xcd_range(st.total, first, stride, count);
+    xcd_range(st, first, stride, count);
     const int tx = threadIdx.x % kBpTile, ty = threadIdx.x / kBpTile;
     for (int gb = first; gb < count; gb += stride) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
-        const SliceDesc sd = bt.sl[s];
+        const SliceDesc sd = load_const(bt.sl, s);
         const int L = sd.L, V = sd.V, B = sd.B;
         const int nt = (L + kBpTile - 1) / kBpTile;
         int lb = gb - st.pre[s];
@@ -179,34 +256,55 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
         float acc = 0.0f;
         if (inside) {
             const float px = sd.X0 + ((float)c + 0.5f) * sd.D, py = sd.X0 + ((float)r + 0.5f) * sd.D;
-            const float half = 0.5f * sd.D;
             const float inv_dg = 1.0f / sd.dgamma;
+            const float wscale = 0.5f * sd.D * 1.01f * inv_dg;
             const float4 *__restrict__ rt = bt.rt0 + sd.ray0 + (long long)i * V * B;
-            const float4 *__restrict__ vt = bt.vt + sd.view0 + (long long)i * V;
             const float *__restrict__ qi = q + sd.sino0 + (long long)i * V * B;
+            const long long v0 = sd.view0 + (long long)i * V;
+            // plane indices of the pixel's lo / hi grid lines
+            const float fc0 = (float)c, fc1 = (float)(c + 1), fr0 = (float)r, fr1 = (float)(r + 1);
             for (int v = 0; v < V; ++v) {
-                const float4 vs = vt[v];   // sx, sy, cos th, sin th
+                const float4 vs = load_const(bt.vt, v0 + v);   // sx, sy, cos th, sin th
+                const int4 vb = load_const(bt.vo, v0 + v);     // sign changes of Ax, Ay over the bins
                 const float dx = px - vs.x, dy = py - vs.y;
                 // (ex, ey): pixel centre in the frame of the central ray
                 const float ex = -(dx * vs.z + dy * vs.w), ey = dx * vs.w - dy * vs.z;
-                const float inv_dist = rsqrtf(dx * dx + dy * dy);
+                const float inv_dist = __builtin_amdgcn_rsqf(dx * dx + dy * dy);
                 const float tq = ey * __builtin_amdgcn_rcpf(ex);
                 const float gam = (ex > 0.0f && fabsf(tq) <= 0.62f) ? fan_atan(tq) : atan2f(ey, ex);
                 // angular half-width of the pixel seen from the source: half-extent
-                // w of the square across the ray over the distance, a second-order
+                // of the square across the ray over the distance, a second-order
                 // bound for the nearer corners, and a small margin in bins
-                const float wq = half * (fabsf(dx) + fabsf(dy)) * inv_dist * inv_dist;
-                const float u = gam * inv_dg + sd.ucenter;
-                const float hw = wq * (1.0f + 2.0f * wq) * 1.01f * inv_dg + 0.01f;
+                const float wq = (fabsf(dx) + fabsf(dy)) * inv_dist * inv_dist;   // over half a pixel
+                const float u = fmaf(gam, inv_dg, sd.ucenter);
+                const float hw = fmaf(wq * wscale, fmaf(wq, sd.D, 1.0f), 0.01f);
                 const int b0 = max(0, (int)ceilf(u - hw));
                 const int b1 = min(B - 1, (int)floorf(u + hw));
-                for (int b = b0; b <= b1; ++b) {
-                    const float4 A = rt[(long long)v * B + b];
-                    const float tx0 = plane_t(c, A.x, A.y), tx1 = plane_t(c + 1, A.x, A.y);
-                    const float ty0 = plane_t(r, A.z, A.w), ty1 = plane_t(r + 1, A.z, A.w);
-                    const float lo = fmaxf(fminf(tx0, tx1), fminf(ty0, ty1));
-                    const float hi = fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1));
-                    acc = fmaf(fmaxf(hi - lo, 0.0f), qi[(long long)v * B + b], acc);
+                const float4 *__restrict__ Av = rt + (long long)v * B;
+                const float *__restrict__ qv = qi + (long long)v * B;
+                if (!((b0 < vb.x && b1 >= vb.x) || (b0 < vb.y && b1 >= vb.y))) {
+                    // every candidate ray has the same direction signs: the lo
+                    // plane of each axis is known, and max/min of the clip reduce
+                    // to one comparison per side (the same values as below)
+                    const bool xpos = ((vb.z & 1) != 0) == (b0 < vb.x);
+                    const bool ypos = ((vb.z & 2) != 0) == (b0 < vb.y);
+                    const float kxl = xpos ? fc0 : fc1, kxh = xpos ? fc1 : fc0;
+                    const float kyl = ypos ? fr0 : fr1, kyh = ypos ? fr1 : fr0;
+                    for (int b = b0; b <= b1; ++b) {
+                        const float4 A = Av[b];
+                        const float lo = fmaxf(fmaf(kxl, A.x, A.y), fmaf(kyl, A.z, A.w));
+                        const float hi = fminf(fmaf(kxh, A.x, A.y), fmaf(kyh, A.z, A.w));
+                        acc = fmaf(fmaxf(hi - lo, 0.0f), qv[b], acc);
+                    }
+                } else {
+                    for (int b = b0; b <= b1; ++b) {
+                        const float4 A = Av[b];
+                        const float tx0 = fmaf(fc0, A.x, A.y), tx1 = fmaf(fc1, A.x, A.y);
+                        const float ty0 = fmaf(fr0, A.z, A.w), ty1 = fmaf(fr1, A.z, A.w);
+                        const float lo = fmaxf(fminf(tx0, tx1), fminf(ty0, ty1));
+                        const float hi = fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1));
+                        acc = fmaf(fmaxf(hi - lo, 0.0f), qv[b], acc);
+                    }
                 }
             }
             fout[sd.img0 + ((long long)i * L + r) * L + c] = acc;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
     const int TCW = 32 + 2 * R, TRH = TH + 2 * S + 2 * R, TS = TCW * TRH;
     const bool same = a.value == a.guide;
     int first, stride, count;
-    xcd_range(st.total, first, stride, count);
+    xcd_range(st, first, stride, count);
     for (int gb = first; gb < count; gb += stride) {
     const int sidx = find_slice(st.pre, bt.ns, gb);
     if (bt.skip && bt.skip[sidx]) continue;

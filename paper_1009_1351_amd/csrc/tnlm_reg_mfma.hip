@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg_mfma(Batch bt, Stage st, Re
     const int n16 = lane & 15, kg = lane >> 4;
 
     int first, stride, count;
-    xcd_range(st.total, first, stride, count);
+    xcd_range(st, first, stride, count);
     for (int gb = first; gb < count; gb += stride) {
         const int sidx = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[sidx]) continue;

@@ -7,9 +7,11 @@ produces (per-phase FBP, TNLM solved to a relative-update tolerance). All
 computation runs in the library's kernels; this module marshals arguments
 and orchestrates.
 
-Fallback rule: the warm start is used for a slice only if the network output
-is finite and its data term (Eq. 1, first part) is not larger than that of
-the FBP of all phases; otherwise the slice starts cold.
+Fallback rule: one outer iteration is run from the network output and one
+from the FBP of all phases; the warm branch is used for a slice only if the
+network output is finite and, after that iteration, its data term (Eq. 1,
+first part) is not larger than the cold branch's. Otherwise the slice
+continues from the cold branch.
 """
 from __future__ import annotations
 
@@ -126,9 +128,14 @@ def data_cost(recon, y, w, f) -> float:
 
 
 def warm_starts(recons, ys, ws, net, batch=4):
-    """f^(0) for each slice (list of Recon contexts of the slices' geometries):
-    network estimate from the per-phase FBPs, or the FBP of all phases when
-    the fallback rule rejects it. Returns (images, used_warm flags)."""
+    """f^(1) for each slice (list of Recon contexts of the slices' geometries).
+
+    The network maps the per-phase FBPs to a start image; one outer iteration
+    is run from it and one from the FBP of all phases, and the warm branch is
+    kept only if its output was finite and its data term after that iteration
+    is not larger than the cold branch's. Both candidates have taken exactly
+    one outer iteration, so the caller continues the solve from the returned
+    images and counts one iteration more. Returns (images, used_warm flags)."""
     fbps = [rc.fbp(y, all_phases=False) for rc, y in zip(recons, ys)]
     outs = [None] * len(recons)
     # group slices of equal shape for batched inference
@@ -143,24 +150,24 @@ def warm_starts(recons, ys, ws, net, batch=4):
             o = net.forward(x)
             for j, k in enumerate(g):
                 outs[k] = o[j].contiguous()
-    f0s, used = [], []
+    f1s, used = [], []
     for rc, y, w, o in zip(recons, ys, ws, outs):
+        cold = rc.step(y, w, rc.fbp(y, all_phases=True))
         ok = bool(torch.isfinite(o).all().item())
-        cold = rc.fbp(y, all_phases=True)
-        if ok and data_cost(rc, y, w, o) <= data_cost(rc, y, w, cold):
-            f0s.append(o)
-            used.append(True)
-        else:
-            f0s.append(cold)
-            used.append(False)
-    return f0s, used
+        if ok:
+            warm = rc.step(y, w, o)
+            ok = bool(torch.isfinite(warm).all().item()) and data_cost(rc, y, w, warm) <= data_cost(rc, y, w, cold)
+        f1s.append(warm if ok else cold)
+        used.append(ok)
+    return f1s, used
 
 
 def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, window=15, log=None):
     """Training pairs produced by the method: (per-phase FBP, TNLM solved to tol).
-    Returns (inputs [n][N][L][L], targets [n][N][L][L]) on the device, plus iterations."""
+    Returns (inputs [n][N][L][L], targets [n][N][L][L]) on the device, the
+    iterations taken and the last relative update of each slice."""
     from .recon import Batch, Recon
-    xs, ts, its = [], [], []
+    xs, ts, its, rels = [], [], [], []
     for s0 in range(0, len(cases), chunk):
         cs = cases[s0:s0 + chunk]
         ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(device) for c in cs]
@@ -169,6 +176,7 @@ def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, win
                    max_outer=max_outer, tol=tol, device=device)
         fs, iters, rel, sts, st = bt.solve(ys, wts)
         its += iters
+        rels += rel
         for c, y, f in zip(cs, ys, fs):
             rc = Recon.from_geometry(c.geom, patch=patch, window=window, h=c.h, mu_hat=c.mu_hat, device=device)
             xs.append(rc.fbp(y, all_phases=False))
@@ -176,7 +184,7 @@ def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, win
         bt.close()
         if log:
             log(f"pairs {min(s0 + chunk, len(cases))}/{len(cases)} (iterations {min(iters)}..{max(iters)})")
-    return torch.stack(xs), torch.stack(ts), its
+    return torch.stack(xs), torch.stack(ts), its, rels
 
 
 def train(net, X, T, *, epochs=4, batch=8, lr=1e-3, lr_final=1e-4, seed=0, log=None, time_limit_s=None):

@@ -117,7 +117,7 @@ def test_corrupted_checkpoint_is_rejected(tmp_path):
 def test_warm_start_pipeline_small():
     from paper_1009_1351_amd.warmstart import WarmStartNet, make_pairs, train, warm_starts
     cases = [synth.make_case("C5train", slice_index=s, L=48, V=24, B=64, patch=5, window=9) for s in range(6)]
-    X, T, its = make_pairs(cases, device=torch.device("cuda"), chunk=6, tol=1e-3, max_outer=60, patch=5, window=9)
+    X, T, its, rels = make_pairs(cases, device=torch.device("cuda"), chunk=6, tol=1e-3, max_outer=60, patch=5, window=9)
     announce(f"pairs: iterations to tol {its}")
     nt = WarmStartNet(phases=10, base=8, seed=1)
     hist = train(nt, X, T, epochs=20, batch=2, lr=2e-3)
@@ -126,8 +126,26 @@ def test_warm_start_pipeline_small():
               for c in cases[:2]]
     ys = [to_dev(c.y) for c in cases[:2]]
     ws = [to_dev(c.w) for c in cases[:2]]
-    f0s, used = warm_starts(recons, ys, ws, nt)
-    assert all(torch.isfinite(f).all() for f in f0s)
-    for rc, y, w, f0 in zip(recons, ys, ws, f0s):
-        f, k, r, st = rc.solve(y, w, f0.clone())
+    f1s, used = warm_starts(recons, ys, ws, nt)
+    assert all(torch.isfinite(f).all() for f in f1s)
+    for rc, y, w, f1, u in zip(recons, ys, ws, f1s, used):
+        # the returned image is one outer iteration from the chosen start
+        cold = rc.step(y, w, rc.fbp(y, all_phases=True))
+        if not u:
+            assert torch.equal(f1, cold)
+        f, k, r, st = rc.solve(y, w, f1.clone())
         assert st == 0 and r < 1e-3
+
+
+def test_warm_start_falls_back_on_absurd_output():
+    from paper_1009_1351_amd.warmstart import WarmStartNet, warm_starts
+    c = synth.make_case("C5train", slice_index=0, L=48, V=24, B=64, patch=5, window=9)
+    nt = WarmStartNet(phases=10, base=8, seed=1)
+    p = nt.get_params()
+    p[-1] = 1e30      # head bias of the last phase -> an output far from any solution
+    nt.set_params(p)
+    rc = recon_for(c.geom, patch=5, window=9, h=c.h, mu_hat=c.mu_hat, init="user", tol=1e-3, max_outer=60)
+    y, w = to_dev(c.y), to_dev(c.w)
+    f1s, used = warm_starts([rc], [y], [w], nt)
+    assert used == [False]
+    assert torch.equal(f1s[0], rc.step(y, w, rc.fbp(y, all_phases=True)))
