@@ -68,11 +68,12 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
+_COMMON = ["paper_1009_1351_amd/csrc/internal.h", "paper_1009_1351_amd/csrc/devutil.h"]
 KERNEL_SOURCES = {
-    "backproject": ["paper_1009_1351_amd/csrc/proj.hip"],
-    "project": ["paper_1009_1351_amd/csrc/proj.hip"],
-    "regularize": ["paper_1009_1351_amd/csrc/tnlm_reg.hip"],
-}
+    "backproject": ["paper_1009_1351_amd/csrc/proj.hip"] + _COMMON,
+    "project": ["paper_1009_1351_amd/csrc/proj.hip"] + _COMMON,
+    "regularize": ["paper_1009_1351_amd/csrc/tnlm_reg.hip"] + _COMMON,
+}   # a change to these files invalidates the stored traffic figures
 
 
 def traffic_for(kernel: str):
@@ -147,7 +148,100 @@ def learned_vs_plain(torch, dev, n_slices, tol=1e-4):
             "warm_start_used": int(sum(used)), "all_reached_tol": bool(all(s == 0 for s in st_l))}
 
 
+KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
+           "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
+
+
+def kind_of(name):
+    for k, v in KIND_OF.items():
+        if k in name:
+            return v
+    return None
+
+
+def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, bench_json):
+    """Write profiles/kernels_c2_batch.md, profiles/traffic_c2_batch.md and
+    profiles/traffic.json from rocprofv3 CSV output (kernel stats, and two
+    counter runs: FETCH_SIZE, WRITE_SIZE, in KiB per dispatch)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(d, pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        if not f:
+            raise SystemExit(f"no {pat} under {d}")
+        return f[0]
+
+    rows = list(csv.DictReader(open(one(kt_dir, "*kernel_stats.csv"))))
+    bj = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    out = ["# Kernel time, C2 batch (3 slices x 10 phases, 256^2, one batched solve per step)", "",
+           "Command (repository root):", "", "    " + command, "",
+           "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:16]:
+        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    kind_ns = defaultdict(lambda: [0.0, 0])
+    for r in rows:
+        k = kind_of(r["Name"])
+        if k:
+            kind_ns[k][0] += float(r["TotalDurationNs"])
+            kind_ns[k][1] += int(r["Calls"])
+    out += ["", "Average per launch by kind (all template instances), against the HIP-event figure "
+                "that bench.py measured in the same run:", "",
+            "| kind | launches | avg ms (trace) |", "|---|---|---|"]
+    for k, (ns, n) in sorted(kind_ns.items()):
+        out.append(f"| {k} | {n} | {ns / n / 1e6:.4f} |")
+    rf = bj.get("roofline", {})
+    out += ["", f"bench.py roofline kernel: {rf.get('kernel')}, avg launch {rf.get('avg_launch_ms')} ms "
+                f"(HIP events), frac {rf.get('frac')} of {rf.get('peak')} {rf.get('unit')}.", ""]
+    open(os.path.join(ROOT, "profiles", "kernels_c2_batch.md"), "w").write("\n".join(out))
+
+    def counters(d):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return per
+
+    fe, wr = counters(fetch_dir), counters(write_dir)
+    copy_bytes = 64 * 1024 * 1024 * 4
+    cf = copy_bytes / 1024 / max(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)
+    cw = copy_bytes / 1024 / max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
+    out = ["# HBM traffic per dispatch, C2 batch", "",
+           "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two counter runs:", "",
+           "    " + counters_command.replace("COUNTER", "FETCH_SIZE"),
+           "    " + counters_command.replace("COUNTER", "WRITE_SIZE"), "",
+           f"Calibration: a 256 MiB device-to-device copy in the same runs reads as "
+           f"{copy_bytes / 1024 / cf:.1f} KiB fetched and {copy_bytes / 1024 / cw:.1f} KiB written, "
+           f"so fetch counts are scaled by {cf:.4f} and write counts by {cw:.4f}.", "",
+           "| kernel | dispatches | fetch KiB (raw) | write KiB (raw) | scaled MB / dispatch |", "|---|---|---|---|---|"]
+    by_kind = defaultdict(lambda: [0.0, 0])
+    for k in fe:
+        if k not in wr or "tnlm::" not in k:
+            continue
+        f_ = sum(fe[k]) / len(fe[k])
+        w_ = sum(wr[k]) / len(wr[k])
+        b = (f_ * cf + w_ * cw) * 1024
+        out.append(f"| `{k[:80]}` | {len(fe[k])} | {f_:.1f} | {w_:.1f} | {b / 1e6:.2f} |")
+        kd = kind_of(k)
+        if kd:
+            by_kind[kd][0] += b * len(fe[k])
+            by_kind[kd][1] += len(fe[k])
+    tj = {}
+    for kd, (b, n) in by_kind.items():
+        if kd in KERNEL_SOURCES:
+            tj[kd] = {"source_hash": source_hash(KERNEL_SOURCES[kd]), "bytes_per_launch": b / n}
+    out += ["", "Per kind (dispatch-weighted mean, scaled bytes): " +
+            ", ".join(f"{k} {v['bytes_per_launch'] / 1e6:.2f} MB" for k, v in sorted(tj.items())), ""]
+    open(os.path.join(ROOT, "profiles", "traffic_c2_batch.md"), "w").write("\n".join(out))
+    json.dump(tj, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+        # bench.py summarize KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON "COMMAND" "COUNTERS_COMMAND"
+        summarize_profiles(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[6], sys.argv[7], sys.argv[5])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
