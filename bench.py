@@ -194,7 +194,8 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
         out.append(f"| {k} | {n} | {ns / n / 1e6:.4f} |")
     rf = bj.get("roofline", {})
     out += ["", f"bench.py roofline kernel: {rf.get('kernel')}, avg launch {rf.get('avg_launch_ms')} ms "
-                f"(HIP events), frac {rf.get('frac')} of {rf.get('peak')} {rf.get('unit')}.", ""]
+                f"(HIP events), frac {rf.get('frac')} of {rf.get('peak')} {rf.get('unit')}.", "",
+            "The bench line of that run:", "", "    " + json.dumps(bj), ""]
     open(os.path.join(ROOT, "profiles", "kernels_c2_batch.md"), "w").write("\n".join(out))
 
     def counters(d):
