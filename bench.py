@@ -110,42 +110,39 @@ def cpu_baseline(case_fn):
                       f"bins, from the FBP image; {dt:.1f} s"}
 
 
-def learned_vs_plain(torch, dev, n_slices, tol=1e-4):
+def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
     """Wall seconds per slice to tol: plain (cold start, one slice at a time)
     against the learned warm start + batched engine, on 512^2 slices."""
     import synth
-    from paper_1009_1351_amd import Batch, Recon
-    from paper_1009_1351_amd.warmstart import WarmStartNet, warm_starts
+    from paper_1009_1351_amd import Recon
+    from paper_1009_1351_amd.warmstart import WarmStartNet, solve_learned
     net = WarmStartNet(phases=10, base=32)
     net.load_weights(WEIGHTS)
     cases = [synth.make_case("C5eval", slice_index=20_000 + k) for k in range(n_slices)]
     c0 = cases[0]
-    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, max_outer=500, tol=tol, device=dev)
+    prm = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat)
     ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(dev) for c in cases]
     ws = [torch.from_numpy(np.asarray(c.w, np.float32)).to(dev) for c in cases]
-    plain = [Recon.from_geometry(c.geom, **kw) for c in cases]
-    recons = [Recon.from_geometry(c.geom, patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, device=dev)
-              for c in cases]
-    bt = Batch([c.geom for c in cases], init="user", **kw)
+    plain = [Recon.from_geometry(c.geom, max_outer=c0.max_outer, tol=tol, device=dev, **prm) for c in cases]
     plain[0].solve(ys[0], ws[0])   # warm-up
+    solve_learned([c.geom for c in cases[:1]], ys[:1], ws[:1], net, tol=tol, max_outer=c0.max_outer,
+                  restart_after=restart_after, device=dev, **prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it_p = [rc.solve(y, w)[1] for rc, y, w in zip(plain, ys, ws)]
+    res = [rc.solve(y, w) for rc, y, w in zip(plain, ys, ws)]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    f1s, used = warm_starts(recons, ys, ws, net)
-    bt.solve(ys, ws, f1s)   # warm-up
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    f1s, used = warm_starts(recons, ys, ws, net)
-    _, it_l, _, st_l, _ = bt.solve(ys, ws, f1s)
+    _, it_l, st_l, used = solve_learned([c.geom for c in cases], ys, ws, net, tol=tol, max_outer=c0.max_outer,
+                                        restart_after=restart_after, device=dev, **prm)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
-    it_l = [k + 1 for k in it_l]   # the first outer iteration ran inside warm_starts
-    return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, to relative update {tol}",
-            "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters_mean": float(np.mean(it_p)),
-            "learned_batched_wall_s_per_slice": t_learned / n_slices, "learned_iters_mean": float(np.mean(it_l)),
-            "warm_start_used": int(sum(used)), "all_reached_tol": bool(all(s == 0 for s in st_l))}
+    return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, h_rel 0.6, "
+                        f"to relative update {tol} (cap {c0.max_outer})",
+            "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters": [r[1] for r in res],
+            "learned_batched_wall_s_per_slice": t_learned / n_slices, "learned_iters": it_l,
+            "warm_start_used": int(sum(used)), "plain_reached_tol": int(sum(r[3] == 0 for r in res)),
+            "learned_reached_tol": int(sum(s_ == 0 for s_ in st_l)), "speedup": t_plain / t_learned}
 
 
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",

@@ -218,6 +218,14 @@ tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches)
 tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, double *out);
 
 /*
+ * Relative change between two image stacks of the context's slice, as used by
+ * the stop rule of the TNLM algorithm box: out = ||a - b|| / max(||a||, 1e-30)
+ * over all phases (double sums, fixed order). Returns TNLM_E_NONFINITE if
+ * either stack holds a NaN or infinity. Synchronises.
+ */
+tnlm_status tnlm_rel_change(tnlm_ctx *ctx, const float *d_a, const float *d_b, double *out);
+
+/*
  * Learned warm start: an encoder-decoder network (4 levels with b, 2b, 4b, 8b
  * channels, two 3x3 convolutions + ReLU per level, 2x2 average pooling,
  * nearest 2x upsampling, skip concatenation, 1x1 head, residual to the input)
@@ -238,6 +246,13 @@ tnlm_status tnlm_cnn_get_params(tnlm_cnn *net, float *host, int64_t n);
 tnlm_status tnlm_cnn_set_params(tnlm_cnn *net, const float *host, int64_t n);
 /* inference: d_out = network(d_in), both [n][N][H][W] float32 device. Async. */
 tnlm_status tnlm_cnn_forward(tnlm_cnn *net, const float *d_in, float *d_out, int32_t n, int32_t H, int32_t W);
+/* inference at a coarser grid: d_in is averaged over factor x factor blocks
+ * (factor 1, 2, 4 or 8; H, W multiples of it), the network runs at
+ * (H/factor, W/factor), and its output is upsampled bilinearly (pixel centres
+ * aligned, edges clamped) into d_out [n][N][H][W]. Lets a network trained at
+ * one pixel size serve slices at a finer one. Async. */
+tnlm_status tnlm_cnn_forward_resampled(tnlm_cnn *net, const float *d_in, float *d_out, int32_t n, int32_t H,
+                                       int32_t W, int32_t factor);
 /* MSE loss (in input_scale units) and its gradient (host_grad nullable, num_params floats). Synchronises. */
 tnlm_status tnlm_cnn_loss_grad(tnlm_cnn *net, const float *d_in, const float *d_target, int32_t n, int32_t H, int32_t W,
                                double *loss, float *host_grad, int64_t ngrad);

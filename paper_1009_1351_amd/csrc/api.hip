@@ -68,6 +68,14 @@ struct Engine {
     float *hfilt = nullptr, *cw = nullptr;
     Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{}, st_tr{};
     float *fT = nullptr;   // transposed copy of the image a projection reads
+    struct StageSpec {
+        Stage *st;
+        std::vector<int> counts;
+        std::vector<double> cost;
+        int *pre, *xb;   // device tables of st
+    };
+    std::vector<StageSpec> specs;
+    std::vector<int> restage_buf;   // host staging of the re-cut tables
     CglsBufs cb{};
     float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
@@ -260,16 +268,20 @@ static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std:
 }
 
 // Work items of a stage: counts[s] items of slice s, each of estimated cost
-// cost[s] (empty: all equal). Besides the prefix table, the item boundaries
-// of the 8 XCD ranges are cut at equal cumulative cost.
-static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &counts, int cap,
-                              const std::vector<double> &cost = {}) {
+// cost[s] (empty: all equal); slices with active[s] == 0 get no items.
+// Besides the prefix table (pre, ns + 1 entries), the item boundaries of the
+// 8 XCD ranges (xb, 9 entries) are cut at equal cumulative cost.
+static void stage_tables(const std::vector<int> &counts, const std::vector<double> &cost,
+                         const std::vector<char> &active, int *pre, int *xb) {
     const size_t ns = counts.size();
-    std::vector<int> pre(ns + 1, 0);
-    for (size_t s = 0; s < ns; ++s) pre[s + 1] = pre[s] + counts[s];
     std::vector<double> cpre(ns + 1, 0.0);
-    for (size_t s = 0; s < ns; ++s) cpre[s + 1] = cpre[s] + counts[s] * (cost.empty() ? 1.0 : cost[s]);
-    std::vector<int> xb(9, 0);
+    pre[0] = 0;
+    for (size_t s = 0; s < ns; ++s) {
+        const int n = active.empty() || active[s] ? counts[s] : 0;
+        pre[s + 1] = pre[s] + n;
+        cpre[s + 1] = cpre[s] + n * (cost.empty() ? 1.0 : cost[s]);
+    }
+    xb[0] = 0;
     for (int x = 1; x < 8; ++x) {
         const double target = cpre[ns] * x / 8.0;
         size_t s = 0;
@@ -279,6 +291,13 @@ static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &coun
         xb[x] = std::max(xb[x - 1], std::min(pre[s] + (int)std::max(0.0, k), pre[s + 1]));
     }
     xb[8] = pre[ns];
+}
+
+static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &counts, int cap,
+                              const std::vector<double> &cost = {}) {
+    const size_t ns = counts.size();
+    std::vector<int> pre(ns + 1, 0), xb(9, 0);
+    stage_tables(counts, cost, {}, pre.data(), xb.data());
     int *d = nullptr, *dx = nullptr;
     HIP_TRY(E.alloc(&d, pre.size()));
     HIP_TRY(hipMemcpy(d, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -286,6 +305,14 @@ static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &coun
     HIP_TRY(hipMemcpy(dx, xb.data(), xb.size() * sizeof(int), hipMemcpyHostToDevice));
     st.pre = d;
     st.xb = dx;
+    // remembered for re-cutting the tables to the slices still running
+    bool found = false;
+    for (auto &sp : E.specs)
+        if (sp.st == &st) {
+            sp = {&st, counts, cost, d, dx};
+            found = true;
+        }
+    if (!found) E.specs.push_back({&st, counts, cost, d, dx});
     st.total = pre.back();
     int g = std::min(st.total, cap);
     if (g >= 8) g -= g % 8;
@@ -540,6 +567,23 @@ static bool ensure_graph(Engine *E, const Batch &bt, const float *y, const float
     return true;
 }
 
+// Re-cut every stage's work tables to the slices with active[s] != 0 (empty:
+// all). Asynchronous on the engine stream, ordered before the next launch; the
+// launches (and a captured graph) keep their configuration.
+static tnlm_status restage(Engine *E, const std::vector<char> &active) {
+    const size_t ns = (size_t)E->ns;
+    HIP_TRY(hipStreamSynchronize(E->stream));   // the previous tables have been copied
+    E->restage_buf.assign(E->specs.size() * (ns + 1 + 9), 0);
+    for (size_t k = 0; k < E->specs.size(); ++k) {
+        auto &sp = E->specs[k];
+        int *pre = E->restage_buf.data() + k * (ns + 10), *xb = pre + ns + 1;
+        stage_tables(sp.counts, sp.cost, active, pre, xb);
+        HIP_TRY(hipMemcpyAsync(sp.pre, pre, (ns + 1) * sizeof(int), hipMemcpyHostToDevice, E->stream));
+        HIP_TRY(hipMemcpyAsync(sp.xb, xb, 9 * sizeof(int), hipMemcpyHostToDevice, E->stream));
+    }
+    return TNLM_OK;
+}
+
 // Full solve on contiguous batch arrays (y, w, f); f holds f^(0) when init is user.
 static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float *f) {
     hipStream_t st = E->stream;
@@ -566,18 +610,31 @@ static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float
     const int K = E->prm.max_outer;
     const bool early = E->prm.tol_rel_update > 0.0f;
     const int chunk = 8;
+    int ndone = 0;   // slices the work tables currently leave out
+    tnlm_status rs = TNLM_OK;
     for (int k = 0; k < K; ++k) {
         if (graph) HIP_TRY(hipGraphLaunch(E->gexec, st));
         else enqueue_step(E, bt, y, w, f);
         if (early && ((k + 1) % chunk == 0) && k + 1 < K) {
             HIP_TRY(hipMemcpyAsync(hf.data(), E->flags, ns * sizeof(int), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
-            bool all = true;
-            for (int s = 0; s < ns; ++s) all = all && hf[s];
-            if (all) break;
+            int done = 0;
+            for (int s = 0; s < ns; ++s) done += hf[s] != 0;
+            if (done == ns) break;
+            // finished slices keep their skip flags; once a quarter of the
+            // batch (or more) has finished since the last cut, re-cut the work
+            // tables so the remaining slices spread over all XCDs again
+            if (ns > 1 && 4 * (done - ndone) >= ns) {
+                std::vector<char> active(ns);
+                for (int s = 0; s < ns; ++s) active[s] = hf[s] == 0;
+                if ((rs = restage(E, active)) != TNLM_OK) break;
+                ndone = done;
+            }
         }
     }
     tnlm_status ls = last_launch();
+    if (ls == TNLM_OK && ndone > 0) ls = restage(E, {});   // full tables for the next call
+    if (rs != TNLM_OK) return rs;
     if (ls != TNLM_OK) return ls;
     HIP_TRY(hipStreamSynchronize(st));
     return TNLM_OK;
@@ -878,6 +935,30 @@ extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const flo
     for (double v : part) s += v;
     *out = s;
     return last_launch();
+}
+
+extern "C" tnlm_status tnlm_rel_change(tnlm_ctx *ctx, const float *d_a, const float *d_b, double *out) {
+    CHECK_CTX();
+    if (!d_a || !d_b || !out) return fail(TNLM_E_INVALID_ARG, "null pointer");
+    Engine *E = &ctx->e;
+    int *bad = E->nonfinite() + E->ns;   // spare flag slot
+    launch_fill_int(bad, 1, 0, E->stream);
+    const int nb = launch_diff_sq(d_a, d_b, E->nimg, E->cost_part, bad, E->stream);
+    std::vector<double> part(2 * nb);
+    int hb = 0;
+    HIP_TRY(hipMemcpyAsync(part.data(), E->cost_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, E->stream));
+    HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, E->stream));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    tnlm_status ls = last_launch();
+    if (ls != TNLM_OK) return ls;
+    if (hb) return fail(TNLM_E_NONFINITE, "non-finite value in an image stack");
+    double d2 = 0.0, a2 = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        d2 += part[2 * k];
+        a2 += part[2 * k + 1];
+    }
+    *out = std::sqrt(d2) / std::max(std::sqrt(a2), 1e-30);
+    return TNLM_OK;
 }
 
 static tnlm_status timing_enable(Engine *E, int32_t enable) {

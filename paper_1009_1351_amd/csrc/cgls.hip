@@ -68,7 +68,7 @@ void launch_copy(const float *src, float *dst, size_t n, hipStream_t st) {
 // Per-slice copy (image- or sinogram-shaped), skipping stopped slices.
 __global__ __launch_bounds__(kBlock) void k_copy_skip(Batch bt, Stage st, int image, const float *__restrict__ a,
                                                       float *__restrict__ b) {
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         SliceDesc sd;
         const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
         if (bt.skip && bt.skip[it.s]) continue;
@@ -87,7 +87,7 @@ void launch_copy_skip(const Batch &b, const Stage &st, bool image, const float *
 // Step m: a = gamma/||q||^2, u += a s (image part), r -= a q and rw = sw r (sinogram part).
 __global__ __launch_bounds__(kBlock) void k_cgls_update(Batch bt, Stage st, CglsBufs cb, int m, int gsel) {
     __shared__ double sh[kBlock];
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         SliceDesc sd;
         const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
         if (bt.skip && bt.skip[it.s]) continue;
@@ -124,7 +124,7 @@ void launch_cgls_update(const Batch &b, const Stage &st, CglsBufs &cb, int m, in
 __global__ __launch_bounds__(kBlock) void k_cgls_direction(Batch bt, Stage st, CglsBufs cb, int m, int gold,
                                                            int gnew) {
     __shared__ double sh[kBlock];
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         SliceDesc sd;
         const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
         if (bt.skip && bt.skip[it.s]) continue;
@@ -149,7 +149,7 @@ void launch_cgls_direction(const Batch &b, const Stage &st, CglsBufs &cb, int m,
 __global__ __launch_bounds__(kBlock) void k_weighted_resid(Batch bt, Stage st, const float *__restrict__ q,
                                                            const float *__restrict__ y, const float *__restrict__ w,
                                                            float *__restrict__ out) {
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         SliceDesc sd;
         const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
         if (bt.skip && bt.skip[it.s]) continue;
@@ -168,7 +168,7 @@ void launch_weighted_resid(const Batch &b, const Stage &st, const float *q, cons
 __global__ __launch_bounds__(kBlock) void k_gradient_step(Batch bt, Stage st, const float *__restrict__ f,
                                                           const float *__restrict__ bp, float inv_beta,
                                                           float *__restrict__ g) {
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         SliceDesc sd;
         const VecItem it = vec_item(st, bt.ns, gb, bt.sl, sd);
         if (bt.skip && bt.skip[it.s]) continue;
@@ -241,6 +241,38 @@ __global__ __launch_bounds__(kBlock) void k_wsq_sum(const float *__restrict__ q,
 int launch_wsq_sum(const float *q, const float *y, const float *w, size_t n, double *part, hipStream_t st) {
     const int nb = std::min(flat_blocks(n), 1024);
     k_wsq_sum<<<nb, kBlock, 0, st>>>(q, y, w, n, part);
+    return nb;
+}
+
+// Partial sums of (a - b)^2 and a^2 (double) and a count of non-finite
+// entries of a or b, for the relative change ||a - b|| / ||a||.
+__global__ __launch_bounds__(kBlock) void k_diff_sq(const float *__restrict__ a, const float *__restrict__ b,
+                                                    size_t n, double *__restrict__ part, int *__restrict__ bad) {
+    __shared__ double sh[kBlock];
+    double d2 = 0.0, a2 = 0.0;
+    int nb = 0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const float x = a[k], z = b[k];
+        if (!isfinite(x) || !isfinite(z)) {
+            ++nb;
+            continue;
+        }
+        const double d = (double)x - (double)z;
+        d2 += d * d;
+        a2 += (double)x * (double)x;
+    }
+    d2 = block_sum_256(d2, sh);
+    a2 = block_sum_256(a2, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = d2;
+        part[2 * blockIdx.x + 1] = a2;
+    }
+    if (nb) atomicAdd(bad, nb);
+}
+
+int launch_diff_sq(const float *a, const float *b, size_t n, double *part, int *bad, hipStream_t st) {
+    const int nb = std::min(flat_blocks(n), 512);
+    k_diff_sq<<<nb, kBlock, 0, st>>>(a, b, n, part, bad);
     return nb;
 }
 

@@ -331,6 +331,48 @@ __global__ void k_count_nonfinite(const float *__restrict__ x, size_t n, int *fl
         if (!isfinite(x[e])) *flag = 1;
 }
 
+// Box average over f x f blocks, [nc][H][W] -> [nc][H/f][W/f] (FP32).
+__global__ void k_box_down(const float *__restrict__ src, float *__restrict__ dst, size_t nc, int H, int W, int f) {
+    const int h = H / f, w = W / f;
+    const size_t n = nc * h * w;
+    const float inv = 1.0f / (float)(f * f);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(e % w);
+        const size_t t = e / w;
+        const int y = (int)(t % h);
+        const size_t c = t / h;
+        const float *s = src + (c * H + (size_t)y * f) * W + (size_t)x * f;
+        float acc = 0.0f;
+        for (int dy = 0; dy < f; ++dy)
+            for (int dx = 0; dx < f; ++dx) acc += s[(size_t)dy * W + dx];
+        dst[e] = acc * inv;
+    }
+}
+
+// Bilinear upsampling by f with pixel centres aligned: output pixel X samples
+// the source at (X + 1/2) / f - 1/2, clamped to the first and last pixel.
+__global__ void k_bilinear_up(const float *__restrict__ src, float *__restrict__ dst, size_t nc, int h, int w,
+                              int f) {
+    const int H = h * f, W = w * f;
+    const size_t n = nc * H * W;
+    const float invf = 1.0f / (float)f;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int X = (int)(e % W);
+        const size_t t = e / W;
+        const int Y = (int)(t % H);
+        const size_t c = t / H;
+        const float sy = fmaxf(((float)Y + 0.5f) * invf - 0.5f, 0.0f);
+        const float sx = fmaxf(((float)X + 0.5f) * invf - 0.5f, 0.0f);
+        const int y0 = min((int)sy, h - 1), x0 = min((int)sx, w - 1);
+        const int y1 = min(y0 + 1, h - 1), x1 = min(x0 + 1, w - 1);
+        const float ay = sy - (float)y0, ax = sx - (float)x0;
+        const float *s = src + c * h * w;
+        const float top = (1.0f - ax) * s[y0 * w + x0] + ax * s[y0 * w + x1];
+        const float bot = (1.0f - ax) * s[y1 * w + x0] + ax * s[y1 * w + x1];
+        dst[e] = (1.0f - ay) * top + ay * bot;
+    }
+}
+
 static int eblocks(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 8192)); }
 
 // ---- launchers used by the host-side network
@@ -387,6 +429,12 @@ void cnn_fill_f32(float *x, size_t n, float v, hipStream_t st) { k_fill_f32<<<eb
 void cnn_fill_bf16(bf16b *x, size_t n, hipStream_t st) { k_fill_bf16<<<eblocks(n), kBlock, 0, st>>>(x, n); }
 void cnn_scale_copy(const float *x, float s, float *y, size_t n, hipStream_t st) {
     k_scale_copy<<<eblocks(n), kBlock, 0, st>>>(x, s, y, n);
+}
+void cnn_box_down(const float *src, float *dst, size_t nc, int H, int W, int f, hipStream_t st) {
+    k_box_down<<<eblocks(nc * (H / f) * (W / f)), kBlock, 0, st>>>(src, dst, nc, H, W, f);
+}
+void cnn_bilinear_up(const float *src, float *dst, size_t nc, int h, int w, int f, hipStream_t st) {
+    k_bilinear_up<<<eblocks(nc * h * w * f * f), kBlock, 0, st>>>(src, dst, nc, h, w, f);
 }
 void cnn_count_nonfinite(const float *x, size_t n, int *flag, hipStream_t st) {
     k_count_nonfinite<<<eblocks(n), kBlock, 0, st>>>(x, n, flag);

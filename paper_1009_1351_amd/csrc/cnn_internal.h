@@ -57,5 +57,7 @@ void cnn_fill_f32(float *x, size_t n, float v, hipStream_t st);
 void cnn_fill_bf16(bf16b *x, size_t n, hipStream_t st);
 void cnn_scale_copy(const float *x, float s, float *y, size_t n, hipStream_t st);
 void cnn_count_nonfinite(const float *x, size_t n, int *flag, hipStream_t st);
+void cnn_box_down(const float *src, float *dst, size_t nc, int H, int W, int f, hipStream_t st);
+void cnn_bilinear_up(const float *src, float *dst, size_t nc, int h, int w, int f, hipStream_t st);
 
 }  // namespace tnlm

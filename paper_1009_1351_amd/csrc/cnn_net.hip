@@ -67,12 +67,14 @@ struct tnlm_cnn {
     bf16b *X, *a1, *cat1, *p1, *a2, *cat2, *p2, *a3, *cat3, *p3, *a4, *b4, *d3a, *d3, *d2a, *d2, *d1a, *d1, *gout;
     bf16b *gd1, *gd1a, *gcat1, *gd2, *gd2a, *gcat2, *gd3, *gd3a, *gcat3, *gb4, *ga4, *gp3, *ga3, *gp2, *ga2, *gp1, *ga1;
     float *outf = nullptr;
+    float *rs = nullptr;   // resampled input and output of tnlm_cnn_forward_resampled
+    size_t rs_cap = 0;
 
     ~tnlm_cnn() {
         (void)hipStreamSynchronize(stream);
         free_acts();
         for (void *p : {(void *)Pm, (void *)G, (void *)M, (void *)V, (void *)Wb, (void *)Wt, (void *)part, (void *)lpart,
-                        (void *)flag})
+                        (void *)flag, (void *)rs})
             if (p) (void)hipFree(p);
     }
     void free_acts() {
@@ -441,6 +443,33 @@ tnlm_status tnlm_cnn_forward(tnlm_cnn *c, const float *d_in, float *d_out, int32
     if ((s = alloc_acts(*c, n, H, W)) != TNLM_OK) return s;
     forward(*c, d_in, n, H, W);
     cnn_scale_copy(c->outf, 1.0f / c->scale, d_out, (size_t)n * c->P * H * W, c->stream);
+    CHIP(hipGetLastError());
+    return TNLM_OK;
+}
+
+tnlm_status tnlm_cnn_forward_resampled(tnlm_cnn *c, const float *d_in, float *d_out, int32_t n, int32_t H, int32_t W,
+                                       int32_t factor) {
+    if (factor == 1) return tnlm_cnn_forward(c, d_in, d_out, n, H, W);
+    if (!c) return cfail(TNLM_E_INVALID_ARG, "null network");
+    if (factor != 2 && factor != 4 && factor != 8) return cfail(TNLM_E_INVALID_ARG, "factor must be 1, 2, 4 or 8");
+    if (n < 1 || H < 1 || W < 1 || H % factor || W % factor)
+        return cfail(TNLM_E_SHAPE, "H and W must be positive multiples of the factor");
+    if (!d_in || !d_out) return cfail(TNLM_E_INVALID_ARG, "null device pointer");
+    const int h = H / factor, w = W / factor;
+    tnlm_status s = check_shape(c, n, h, w);
+    if (s != TNLM_OK) return s;
+    const size_t ns = (size_t)n * c->P * h * w;
+    if (c->rs_cap < 2 * ns) {
+        CHIP(hipStreamSynchronize(c->stream));
+        if (c->rs) (void)hipFree(c->rs);
+        c->rs = nullptr;
+        c->rs_cap = 0;
+        CHIP(hipMalloc(&c->rs, 2 * ns * sizeof(float)));
+        c->rs_cap = 2 * ns;
+    }
+    cnn_box_down(d_in, c->rs, (size_t)n * c->P, H, W, factor, c->stream);
+    if ((s = tnlm_cnn_forward(c, c->rs, c->rs + ns, n, h, w)) != TNLM_OK) return s;
+    cnn_bilinear_up(c->rs + ns, d_out, (size_t)n * c->P, h, w, factor, c->stream);
     CHIP(hipGetLastError());
     return TNLM_OK;
 }

@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kBlock) void k_fbp_filter(Batch bt, Stage st, const
                                                        const float *__restrict__ cw, const float *__restrict__ hf,
                                                        float *__restrict__ Q) {
     extern __shared__ float rp[];
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
         const SliceDesc sd = bt.sl[s];
@@ -43,7 +43,7 @@ int fbp_bp_blocks(const SliceDesc &s, int all_phases) {
 __global__ __launch_bounds__(kBlock) void k_fbp_backproject(Batch bt, Stage st, const float *__restrict__ Q,
                                                             float *__restrict__ f, int all_phases) {
     const int tx = threadIdx.x % kFbpTile, ty = threadIdx.x / kFbpTile;
-    for (int gb = blockIdx.x; gb < st.total; gb += gridDim.x) {
+    for (int gb = blockIdx.x, gend = stage_total(st); gb < gend; gb += gridDim.x) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
         const SliceDesc sd = bt.sl[s];

@@ -72,6 +72,10 @@ __device__ __forceinline__ T load_const(const T *p, long long i) {
     return out;
 }
 
+// Work items currently in a stage (the device table, which the host may
+// re-cut between launches; Stage::total is the count at set-up).
+__device__ __forceinline__ int stage_total(const Stage &st) { return load_const(st.xb, 8); }
+
 // Block index -> (slice, local block). Block-uniform.
 __device__ __forceinline__ int find_slice(const int *pre, int ns, int gb) {
     int lo = 0, hi = ns - 1;
@@ -87,14 +91,16 @@ __device__ __forceinline__ int find_slice(const int *pre, int ns, int gb) {
 // turn; each XCD gets a contiguous range of work items, so that the blocks
 // sharing an XCD (and its L2) work on the same slices and phases. The ranges
 // are cut on the host to equal estimated cost (slices of a batch differ in
-// size and view count), not to equal item counts.
+// size and view count), not to equal item counts. The tables live in device
+// memory, so the host can re-cut them between launches (when slices of a
+// batch have converged) without changing the launch itself.
 __device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stride, int &count) {
     const int nx = 8;
     const int g = (int)gridDim.x;
     if (g < nx) {   // fewer blocks than XCDs: plain grid-stride order
         first = (int)blockIdx.x;
         stride = g;
-        count = st.total;
+        count = load_const(st.xb, nx);
         return;
     }
     const int x = (int)blockIdx.x % nx;
@@ -142,6 +148,8 @@ void launch_finalize(const Batch &b, const double *relpart, float tol, float *hi
 void launch_check_finite(const float *a, size_t n, int *flag, hipStream_t st);
 void launch_fill_int(int *a, int n, int v, hipStream_t st);
 int launch_wsq_sum(const float *q, const float *y, const float *w, size_t n, double *part, hipStream_t st);
+// partials [2 * blocks] of ||a - b||^2 and ||a||^2; *bad += non-finite entries (set it to 0 first)
+int launch_diff_sq(const float *a, const float *b, size_t n, double *part, int *bad, hipStream_t st);
 
 // ---- TNLM regulariser (tnlm_reg.hip)
 int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane);

@@ -32,45 +32,65 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=500):
+def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=600, restart_after=64):
+    """Plain (one slice at a time, cold start) against learned + batched
+    (warm starts, one batched solve, cold restart of slices still above the
+    tolerance after restart_after iterations), on the same slices."""
     from paper_1009_1351_amd.recon import Batch, Recon
-    from paper_1009_1351_amd.warmstart import warm_starts
+    from paper_1009_1351_amd.warmstart import solve_learned
     c0 = cases[0]
-    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, max_outer=max_outer, tol=tol, device=dev)
+    prm = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat)
     ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(dev) for c in cases]
     ws = [torch.from_numpy(np.asarray(c.w, np.float32)).to(dev) for c in cases]
     geoms = [c.geom for c in cases]
-    cold_b = Batch(geoms, init="fbp", **kw)
-    warm_b = Batch(geoms, init="user", **kw)
-    recons = [Recon.from_geometry(g, patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, device=dev)
-              for g in geoms]
-    # warm-up of the inference path (activation buffers at this size); the
-    # solves themselves are long enough that graph capture is negligible
-    net.forward(torch.stack([recons[0].fbp(ys[0], all_phases=False)]))
+    n = len(cases)
+    # warm-up: inference buffers at this size, one plain solve
+    net.forward(torch.stack([Recon.from_geometry(geoms[0], device=dev, **prm).fbp(ys[0], all_phases=False)]),
+                factor=net.factor_for(c0.geom.L))
+    plain = [Recon.from_geometry(g, max_outer=max_outer, tol=tol, device=dev, **prm) for g in geoms]
+    plain[0].solve(ys[0], ws[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fc, it_c, rel_c, st_c, _ = cold_b.solve(ys, ws)
+    res_p = [rc.solve(y, w) for rc, y, w in zip(plain, ys, ws)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    fp = [r[0] for r in res_p]
+    it_p = [r[1] for r in res_p]
+    st_p = [r[3] for r in res_p]
+    # batched cold (no network), to separate the two effects
+    cold_b = Batch(geoms, init="fbp", max_outer=max_outer, tol=tol, device=dev, **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it_c, _, st_c, _ = cold_b.solve(ys, ws)
     torch.cuda.synchronize()
     t_cold = time.perf_counter() - t0
+    cold_b.close()
     t0 = time.perf_counter()
-    f1s, used = warm_starts(recons, ys, ws, net)
-    fw, it_w, rel_w, st_w, _ = warm_b.solve(ys, ws, f1s)
+    fl, it_l, st_l, used = solve_learned(geoms, ys, ws, net, tol=tol, max_outer=max_outer,
+                                         restart_after=restart_after, device=dev, **prm)
     torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t0
-    it_w = [k + 1 for k in it_w]   # the first outer iteration ran inside warm_starts
-    diff = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(fw, fc)]
-    truth_err_c = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fc, cases)]
-    truth_err_w = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fw, cases)]
-    n = len(cases)
+    t_learned = time.perf_counter() - t0
+    diff = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(fl, fp)]
+    err_p = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fp, cases)]
+    err_l = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fl, cases)]
+
+    def arm(its, sts, t):
+        conv = [k for k, s_ in zip(its, sts) if s_ == 0]
+        return {"wall_s_per_slice": t / n, "iters_mean": float(np.mean(its)), "iters_median": float(np.median(its)),
+                "reached_tol": len(conv), "iters": its}
+
+    both = [j for j in range(n) if st_p[j] == 0 and st_l[j] == 0]
     return {
-        "slices": n, "tol": tol,
-        "cold": {"iters_mean": float(np.mean(it_c)), "iters": it_c, "wall_s_per_slice": t_cold / n,
-                 "all_reached_tol": bool(all(s == 0 for s in st_c)), "last_rel": rel_c},
-        "warm": {"iters_mean": float(np.mean(it_w)), "iters": it_w, "wall_s_per_slice": t_warm / n,
-                 "all_reached_tol": bool(all(s == 0 for s in st_w)), "last_rel": rel_w, "warm_used": used},
-        "final_rel_diff_warm_vs_cold": {"max": max(diff), "mean": float(np.mean(diff))},
-        "rel_err_to_phantom": {"cold_mean": float(np.mean(truth_err_c)), "warm_mean": float(np.mean(truth_err_w))},
-        "speedup_wall": (t_cold / n) / (t_warm / n),
+        "slices": n, "tol": tol, "max_outer": max_outer, "restart_after": restart_after,
+        "plain": arm(it_p, st_p, t_plain),
+        "batched_cold": arm(it_c, st_c, t_cold),
+        "learned_batched": {**arm(it_l, st_l, t_learned), "warm_used": int(sum(used))},
+        "speedup_learned_batched_vs_plain": t_plain / t_learned,
+        "on_slices_reaching_tol_in_both": {"count": len(both),
+                                           "plain_iters_mean": float(np.mean([it_p[j] for j in both])) if both else None,
+                                           "learned_iters_mean": float(np.mean([it_l[j] for j in both])) if both else None},
+        "final_rel_diff_learned_vs_plain": {"max": max(diff), "mean": float(np.mean(diff))},
+        "rel_err_to_phantom": {"plain_mean": float(np.mean(err_p)), "learned_mean": float(np.mean(err_l))},
     }
 
 
@@ -80,7 +100,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=2000)
     ap.add_argument("--pair-tol", type=float, default=1e-4)
-    ap.add_argument("--pair-max-outer", type=int, default=400)
+    ap.add_argument("--pair-max-outer", type=int, default=600)
     ap.add_argument("--pair-time", type=float, default=480.0, help="seconds budget for pair generation")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8)
@@ -89,7 +109,8 @@ def main():
     ap.add_argument("--eval-slices", type=int, default=32)
     ap.add_argument("--eval-L", type=int, default=512)
     ap.add_argument("--eval-B", type=int, default=720)
-    ap.add_argument("--eval-max-outer", type=int, default=500)
+    ap.add_argument("--eval-max-outer", type=int, default=600)
+    ap.add_argument("--restart-after", type=int, default=64)
     ap.add_argument("--out", default="warmstart.ckpt")
     ap.add_argument("--ckpt", default=None)
     ap.add_argument("--eval-only", action="store_true")
@@ -97,7 +118,7 @@ def main():
     a = ap.parse_args()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    net = WarmStartNet(phases=10, base=32, seed=a.seed)
+    net = WarmStartNet(phases=10, base=32, seed=a.seed, train_L=synth.CONFIGS["C5train"]["L"])
     report = {"network": {"levels": 4, "base_channels": 32, "params": net.num_params}}
     if a.ckpt:
         if a.ckpt.endswith(".npz"):
@@ -136,7 +157,7 @@ def main():
         torch.cuda.empty_cache()
     ev = [synth.make_case("C5eval", slice_index=10_000 + k, L=a.eval_L, B=a.eval_B) for k in range(a.eval_slices)]
     log("evaluation ...")
-    report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer)
+    report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after)
     print(json.dumps(report), flush=True)
 
 

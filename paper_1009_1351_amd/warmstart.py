@@ -7,11 +7,17 @@ produces (per-phase FBP, TNLM solved to a relative-update tolerance). All
 computation runs in the library's kernels; this module marshals arguments
 and orchestrates.
 
-Fallback rule: one outer iteration is run from the network output and one
-from the FBP of all phases; the warm branch is used for a slice only if the
-network output is finite and, after that iteration, its data term (Eq. 1,
-first part) is not larger than the cold branch's. Otherwise the slice
-continues from the cold branch.
+Resolution: the network runs at the pixel size it was trained at; a slice
+whose side is 2, 4 or 8 times the training side is averaged down to it and
+the prediction upsampled bilinearly (tnlm_cnn_forward_resampled).
+
+Fallback rule: two outer iterations are run from the network output and two
+from the FBP of all phases; the warm branch is used for a slice only if its
+iterates are finite and its relative update in the second iteration is not
+larger than the cold branch's (a start nearer the fixed point moves less;
+the first iteration is not used because it mostly removes the network's
+high-frequency error). Otherwise the slice continues from the cold branch.
+Either way the solve continues from the kept branch's second iterate.
 """
 from __future__ import annotations
 
@@ -22,14 +28,19 @@ import numpy as np
 import torch
 
 from . import _native as nat
-from ._native import check, check_cnn
+from ._native import TnlmError, check, check_cnn
 from .recon import _norm_device
 
 
+# outer iterations that warm_starts runs before handing the slices back
+WARM_START_ITERS = 2
+
+
 class WarmStartNet:
-    def __init__(self, phases=10, base=32, seed=0, scale=50.0, device=None):
+    def __init__(self, phases=10, base=32, seed=0, scale=50.0, train_L=None, device=None):
         self.device = _norm_device(device)
         self.phases, self.base, self.scale = int(phases), int(base), float(scale)
+        self.train_L = train_L   # image side of the training pairs (None: run at any size as given)
         self._n = C.c_void_p()
         with torch.cuda.device(self.device):
             check_cnn(nat.lib.tnlm_cnn_create(C.byref(self._n), self.phases, self.base, int(seed), self.scale,
@@ -65,10 +76,18 @@ class WarmStartNet:
             raise ValueError(f"{name} must be a contiguous float32 [n][{self.phases}][H][W] tensor on {self.device}")
         return C.c_void_p(x.data_ptr())
 
-    def forward(self, x, out=None):
+    def factor_for(self, L):
+        """Down-sampling factor that brings side L to the training side (1 if none applies)."""
+        if not self.train_L or L % self.train_L:
+            return 1
+        f = L // self.train_L
+        return f if f in (1, 2, 4, 8) else 1
+
+    def forward(self, x, out=None, factor=1):
         out = torch.empty_like(x) if out is None else out
         n, _, H, W = x.shape
-        check_cnn(nat.lib.tnlm_cnn_forward(self._n, self._chk(x, "x"), self._chk(out, "out"), n, H, W))
+        check_cnn(nat.lib.tnlm_cnn_forward_resampled(self._n, self._chk(x, "x"), self._chk(out, "out"), n, H, W,
+                                                     int(factor)))
         return out
 
     def loss_grad(self, x, t, want_grad=True):
@@ -99,7 +118,7 @@ class WarmStartNet:
         bits = p[:nw].view(np.uint32)
         w16 = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.uint16)
         np.savez(path, w_bf16=w16, bias=p[nw:], meta=np.array([self.phases, self.base], np.int64),
-                 scale=np.array([self.scale], np.float32))
+                 scale=np.array([self.scale], np.float32), train_L=np.array([self.train_L or 0], np.int64))
 
     def load_weights(self, path):
         z = np.load(path, allow_pickle=False)
@@ -108,6 +127,8 @@ class WarmStartNet:
             raise ValueError("weights are for a different network shape or input scale")
         w = (z["w_bf16"].astype(np.uint32) << 16).view(np.float32)
         self.set_params(np.concatenate([w, z["bias"].astype(np.float32)]))
+        if "train_L" in z.files and int(z["train_L"][0]) > 0:
+            self.train_L = int(z["train_L"][0])
 
     def _num_weights(self) -> int:
         b, P = self.base, self.phases
@@ -127,39 +148,83 @@ def data_cost(recon, y, w, f) -> float:
     return out.value
 
 
-def warm_starts(recons, ys, ws, net, batch=4):
-    """f^(1) for each slice (list of Recon contexts of the slices' geometries).
+def rel_change(recon, a, b) -> float:
+    """||a - b|| / ||a|| over the slice's image stack (raises TnlmError on non-finite values)."""
+    out = C.c_double(0.0)
+    check(nat.lib.tnlm_rel_change(recon._ctx, recon._img(a, "a"), recon._img(b, "b"), C.byref(out)))
+    return out.value
 
-    The network maps the per-phase FBPs to a start image; one outer iteration
-    is run from it and one from the FBP of all phases, and the warm branch is
-    kept only if its output was finite and its data term after that iteration
-    is not larger than the cold branch's. Both candidates have taken exactly
-    one outer iteration, so the caller continues the solve from the returned
-    images and counts one iteration more. Returns (images, used_warm flags)."""
+
+def _second_move(rc, y, w, f):
+    """Two outer iterations in place on f; returns the relative update of the second."""
+    rc.step(y, w, f)
+    prev = f.clone()
+    rc.step(y, w, f)
+    return rel_change(rc, f, prev)
+
+
+def warm_starts(recons, ys, ws, net, batch=4):
+    """Start images for each slice (list of Recon contexts of the slices'
+    geometries), each WARM_START_ITERS outer iterations in: from the network
+    estimate, or from the FBP of all phases when the fallback rule rejects
+    it. Returns (images, used_warm flags)."""
     fbps = [rc.fbp(y, all_phases=False) for rc, y in zip(recons, ys)]
     outs = [None] * len(recons)
-    # group slices of equal shape for batched inference
-    order = sorted(range(len(recons)), key=lambda k: (recons[k].L,))
-    for start in range(0, len(order), batch):
-        grp = [k for k in order[start:start + batch] if recons[k].L == recons[order[start]].L]
-        rest = [k for k in order[start:start + batch] if k not in grp]
-        for g in (grp, rest):
-            if not g:
-                continue
-            x = torch.stack([fbps[k] for k in g])
-            o = net.forward(x)
-            for j, k in enumerate(g):
-                outs[k] = o[j].contiguous()
-    f1s, used = [], []
+    # batched inference over slices of equal size
+    order = sorted(range(len(recons)), key=lambda k: recons[k].L)
+    k = 0
+    while k < len(order):
+        L = recons[order[k]].L
+        grp = [j for j in order[k:k + batch] if recons[j].L == L]
+        x = torch.stack([fbps[j] for j in grp])
+        o = net.forward(x, factor=net.factor_for(L))
+        for t, j in enumerate(grp):
+            outs[j] = o[t].contiguous()
+        k += len(grp)
+    f_out, used = [], []
     for rc, y, w, o in zip(recons, ys, ws, outs):
-        cold = rc.step(y, w, rc.fbp(y, all_phases=True))
-        ok = bool(torch.isfinite(o).all().item())
-        if ok:
-            warm = rc.step(y, w, o)
-            ok = bool(torch.isfinite(warm).all().item()) and data_cost(rc, y, w, warm) <= data_cost(rc, y, w, cold)
-        f1s.append(warm if ok else cold)
+        cold = rc.fbp(y, all_phases=True)
+        m_cold = _second_move(rc, y, w, cold)
+        try:
+            m_warm = _second_move(rc, y, w, o)
+            ok = m_warm <= m_cold
+        except TnlmError:   # non-finite iterate
+            ok = False
+        f_out.append(o if ok else cold)
         used.append(ok)
-    return f1s, used
+    return f_out, used
+
+
+def solve_learned(geoms, ys, ws, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
+    """Learned + batched solve of many slices to a relative-update tolerance.
+
+    Warm starts (warm_starts) for all slices, then one batched solve. A slice
+    still above the tolerance after `restart_after` further iterations (the
+    TNLM outer iteration can settle into a period-2 cycle instead of
+    converging) restarts cold, from the FBP of all phases, in a second batched
+    solve with the remaining iteration budget. Returns (images, iterations
+    per slice counted from the start, statuses, used_warm)."""
+    from .recon import Batch, Recon
+    kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=device)
+    recons = [Recon.from_geometry(g, **kw) for g in geoms]
+    fs, used = warm_starts(recons, ys, ws, net)
+    k1 = max_outer - WARM_START_ITERS if restart_after is None else min(restart_after, max_outer - WARM_START_ITERS)
+    bt = Batch(geoms, init="user", max_outer=k1, tol=tol, **kw)
+    fs, it, _, st, _ = bt.solve(ys, ws, fs)
+    bt.close()
+    iters = [WARM_START_ITERS + k for k in it]
+    redo = [j for j in range(len(geoms)) if st[j] != 0]
+    left = max_outer - WARM_START_ITERS - k1
+    if redo and left > 0:
+        b2 = Batch([geoms[j] for j in redo], init="fbp", max_outer=left, tol=tol, **kw)
+        f2, it2, _, st2, _ = b2.solve([ys[j] for j in redo], [ws[j] for j in redo])
+        b2.close()
+        for t, j in enumerate(redo):
+            fs[j], st[j] = f2[t], st2[t]
+            iters[j] += it2[t]
+    for rc in recons:
+        rc.close()
+    return fs, iters, st, used
 
 
 def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, window=15, log=None):
@@ -213,4 +278,5 @@ def train(net, X, T, *, epochs=4, batch=8, lr=1e-3, lr_final=1e-4, seed=0, log=N
     return hist
 
 
-__all__ = ["WarmStartNet", "warm_starts", "make_pairs", "train", "data_cost"]
+__all__ = ["WarmStartNet", "warm_starts", "solve_learned", "make_pairs", "train", "data_cost", "rel_change",
+           "WARM_START_ITERS"]

@@ -129,12 +129,37 @@ def test_warm_start_pipeline_small():
     f1s, used = warm_starts(recons, ys, ws, nt)
     assert all(torch.isfinite(f).all() for f in f1s)
     for rc, y, w, f1, u in zip(recons, ys, ws, f1s, used):
-        # the returned image is one outer iteration from the chosen start
-        cold = rc.step(y, w, rc.fbp(y, all_phases=True))
+        # the returned image is WARM_START_ITERS outer iterations from the chosen start
+        cold = cold_start(rc, y, w)
         if not u:
             assert torch.equal(f1, cold)
         f, k, r, st = rc.solve(y, w, f1.clone())
         assert st == 0 and r < 1e-3
+
+
+def cold_start(rc, y, w):
+    from paper_1009_1351_amd.warmstart import WARM_START_ITERS
+    f = rc.fbp(y, all_phases=True)
+    for _ in range(WARM_START_ITERS):
+        rc.step(y, w, f)
+    return f
+
+
+def test_resampled_inference_matches_pool_net_upsample():
+    # tnlm_cnn_forward_resampled = box average -> network -> bilinear upsample
+    import torch.nn.functional as F
+    nt = net(10, 8, seed=2)
+    p = nt.get_params()
+    rng = np.random.default_rng(3)
+    p[:] = (rng.standard_normal(p.size) * 0.05).astype(np.float32)
+    nt.set_params(p)
+    x = to_dev(rng.uniform(0.0, 0.03, size=(2, 10, 64, 64))).reshape(2, 10, 64, 64)
+    got = nt.forward(x, factor=2)
+    small = F.avg_pool2d(x, 2).contiguous()
+    ref = F.interpolate(nt.forward(small), scale_factor=2, mode="bilinear", align_corners=False)
+    err = float((got - ref).abs().max() / ref.abs().max())
+    announce(f"resampled inference vs pool/net/upsample: max rel {err:.2e}")
+    assert err < 1e-3
 
 
 def test_warm_start_falls_back_on_absurd_output():
@@ -148,4 +173,4 @@ def test_warm_start_falls_back_on_absurd_output():
     y, w = to_dev(c.y), to_dev(c.w)
     f1s, used = warm_starts([rc], [y], [w], nt)
     assert used == [False]
-    assert torch.equal(f1s[0], rc.step(y, w, rc.fbp(y, all_phases=True)))
+    assert torch.equal(f1s[0], cold_start(rc, y, w))
