@@ -216,7 +216,15 @@ void launch_project(const Batch &b, const Stage &st, int mode, const float *f, c
 // source; a conservative range is enumerated and each candidate's exact clip
 // is computed with plane_t. Rays that miss the pixel add l = 0.
 // ---------------------------------------------------------------------------
-constexpr int kBpTile = 16;
+// Each lane gathers a 2 x 2 block of pixels; a block of 256 lanes covers a
+// 32 x 32 tile. The candidate bins of a view are those of the 2 x 2 square
+// (a superset of each pixel's own), found once per lane and view; the three
+// x-planes and three y-planes of the square serve its four pixels. A
+// candidate ray that misses a pixel adds exactly zero, so every pixel
+// receives the same contributions in the same order as a gather over its
+// own candidate range.
+constexpr int kBpTile = 32;
+constexpr int kBpLanes = kBpTile / 2;   // lanes per tile side
 
 // atan(t) for |t| <= 0.62 (|angle| <= 0.555 rad, beyond the fan half-angle of
 // the scanner): t * p(t^2), p of degree 4 fitted by weighted least squares on
@@ -230,6 +238,31 @@ __device__ __forceinline__ float fan_atan(float t) {
     return t * p;
 }
 
+// Candidate loop of one lane and view with the direction signs of all
+// candidate rays fixed (XP: T_x grows with the plane index; YP likewise):
+// planes c, c+1, c+2 (and r, r+1, r+2) are evaluated once and take the lo or
+// hi role of each pixel by the signs.
+template <bool XP, bool YP>
+__device__ __forceinline__ void bp_block_oriented(const float4 *__restrict__ Av, const float *__restrict__ qv, int b0,
+                                                  int b1, float fc0, float fr0, float &a00, float &a01, float &a10,
+                                                  float &a11) {
+    const float fc1 = fc0 + 1.0f, fc2 = fc0 + 2.0f, fr1 = fr0 + 1.0f, fr2 = fr0 + 2.0f;
+    for (int b = b0; b <= b1; ++b) {
+        const float4 A = Av[b];
+        const float qb = qv[b];
+        const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
+        const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
+        const float xl0 = XP ? X0 : X1, xh0 = XP ? X1 : X0;   // column c
+        const float xl1 = XP ? X1 : X2, xh1 = XP ? X2 : X1;   // column c + 1
+        const float yl0 = YP ? Y0 : Y1, yh0 = YP ? Y1 : Y0;   // row r
+        const float yl1 = YP ? Y1 : Y2, yh1 = YP ? Y2 : Y1;   // row r + 1
+        a00 = fmaf(fmaxf(fminf(xh0, yh0) - fmaxf(xl0, yl0), 0.0f), qb, a00);
+        a01 = fmaf(fmaxf(fminf(xh1, yh0) - fmaxf(xl1, yl0), 0.0f), qb, a01);
+        a10 = fmaf(fmaxf(fminf(xh0, yh1) - fmaxf(xl0, yl1), 0.0f), qb, a10);
+        a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
+    }
+}
+
 int bp_blocks(const SliceDesc &s) {
     const int t = (s.L + kBpTile - 1) / kBpTile;
     return s.N * t * t;
@@ -240,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
     __shared__ double sh[kBlock];
     int first, stride, count;
     xcd_range(st, first, stride, count);
-    const int tx = threadIdx.x % kBpTile, ty = threadIdx.x / kBpTile;
+    const int tx = threadIdx.x % kBpLanes, ty = threadIdx.x / kBpLanes;
     for (int gb = first; gb < count; gb += stride) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
@@ -251,66 +284,86 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
         const int tcx = lb % nt;
         lb /= nt;
         const int tcy = lb % nt, i = lb / nt;
-        const int c = tcx * kBpTile + tx, r = tcy * kBpTile + ty;
-        const bool inside = c < L && r < L;
-        float acc = 0.0f;
-        if (inside) {
-            const float px = sd.X0 + ((float)c + 0.5f) * sd.D, py = sd.X0 + ((float)r + 0.5f) * sd.D;
+        const int c = tcx * kBpTile + 2 * tx, r = tcy * kBpTile + 2 * ty;   // lower-left pixel of the 2 x 2 block
+        const bool any = c < L && r < L;
+        float a00 = 0.0f, a01 = 0.0f, a10 = 0.0f, a11 = 0.0f;   // a<row><col>
+        if (any) {
+            // centre of the 2 x 2 square (a grid corner) and its half-side D
+            const float px = sd.X0 + (float)(c + 1) * sd.D, py = sd.X0 + (float)(r + 1) * sd.D;
             const float inv_dg = 1.0f / sd.dgamma;
-            const float wscale = 0.5f * sd.D * 1.01f * inv_dg;
+            const float wscale = sd.D * 1.01f * inv_dg;
             const float4 *__restrict__ rt = bt.rt0 + sd.ray0 + (long long)i * V * B;
             const float *__restrict__ qi = q + sd.sino0 + (long long)i * V * B;
             const long long v0 = sd.view0 + (long long)i * V;
-            // plane indices of the pixel's lo / hi grid lines
-            const float fc0 = (float)c, fc1 = (float)(c + 1), fr0 = (float)r, fr1 = (float)(r + 1);
+            const float fc0 = (float)c, fc1 = (float)(c + 1), fc2 = (float)(c + 2);
+            const float fr0 = (float)r, fr1 = (float)(r + 1), fr2 = (float)(r + 2);
             for (int v = 0; v < V; ++v) {
                 const float4 vs = load_const(bt.vt, v0 + v);   // sx, sy, cos th, sin th
                 const int4 vb = load_const(bt.vo, v0 + v);     // sign changes of Ax, Ay over the bins
                 const float dx = px - vs.x, dy = py - vs.y;
-                // (ex, ey): pixel centre in the frame of the central ray
+                // (ex, ey): square centre in the frame of the central ray
                 const float ex = -(dx * vs.z + dy * vs.w), ey = dx * vs.w - dy * vs.z;
                 const float inv_dist = __builtin_amdgcn_rsqf(dx * dx + dy * dy);
                 const float tq = ey * __builtin_amdgcn_rcpf(ex);
                 const float gam = (ex > 0.0f && fabsf(tq) <= 0.62f) ? fan_atan(tq) : atan2f(ey, ex);
-                // angular half-width of the pixel seen from the source: half-extent
-                // of the square across the ray over the distance, a second-order
+                // angular half-width of the square seen from the source: its
+                // half-extent across the ray over the distance, a second-order
                 // bound for the nearer corners, and a small margin in bins
-                const float wq = (fabsf(dx) + fabsf(dy)) * inv_dist * inv_dist;   // over half a pixel
+                const float wq = (fabsf(dx) + fabsf(dy)) * inv_dist * inv_dist;   // over the half-side
                 const float u = fmaf(gam, inv_dg, sd.ucenter);
-                const float hw = fmaf(wq * wscale, fmaf(wq, sd.D, 1.0f), 0.01f);
+                const float hw = fmaf(wq * wscale, fmaf(wq, 2.0f * sd.D, 1.0f), 0.01f);
                 const int b0 = max(0, (int)ceilf(u - hw));
                 const int b1 = min(B - 1, (int)floorf(u + hw));
                 const float4 *__restrict__ Av = rt + (long long)v * B;
                 const float *__restrict__ qv = qi + (long long)v * B;
                 if (!((b0 < vb.x && b1 >= vb.x) || (b0 < vb.y && b1 >= vb.y))) {
-                    // every candidate ray has the same direction signs: the lo
-                    // plane of each axis is known, and max/min of the clip reduce
-                    // to one comparison per side (the same values as below)
+                    // every candidate ray has the same direction signs: the lo and
+                    // hi plane of each pixel along each axis are known, and the clip
+                    // max(min(..), min(..)) / min(max(..), max(..)) reduces to one
+                    // comparison per side (the same values as the general form)
                     const bool xpos = ((vb.z & 1) != 0) == (b0 < vb.x);
                     const bool ypos = ((vb.z & 2) != 0) == (b0 < vb.y);
-                    const float kxl = xpos ? fc0 : fc1, kxh = xpos ? fc1 : fc0;
-                    const float kyl = ypos ? fr0 : fr1, kyh = ypos ? fr1 : fr0;
-                    for (int b = b0; b <= b1; ++b) {
-                        const float4 A = Av[b];
-                        const float lo = fmaxf(fmaf(kxl, A.x, A.y), fmaf(kyl, A.z, A.w));
-                        const float hi = fminf(fmaf(kxh, A.x, A.y), fmaf(kyh, A.z, A.w));
-                        acc = fmaf(fmaxf(hi - lo, 0.0f), qv[b], acc);
+                    if (xpos) {
+                        if (ypos) bp_block_oriented<true, true>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        else bp_block_oriented<true, false>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                    } else {
+                        if (ypos) bp_block_oriented<false, true>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        else bp_block_oriented<false, false>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
                     }
                 } else {
                     for (int b = b0; b <= b1; ++b) {
                         const float4 A = Av[b];
-                        const float tx0 = fmaf(fc0, A.x, A.y), tx1 = fmaf(fc1, A.x, A.y);
-                        const float ty0 = fmaf(fr0, A.z, A.w), ty1 = fmaf(fr1, A.z, A.w);
-                        const float lo = fmaxf(fminf(tx0, tx1), fminf(ty0, ty1));
-                        const float hi = fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1));
-                        acc = fmaf(fmaxf(hi - lo, 0.0f), qv[b], acc);
+                        const float qb = qv[b];
+                        const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
+                        const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
+                        const float xl0 = fminf(X0, X1), xh0 = fmaxf(X0, X1), xl1 = fminf(X1, X2), xh1 = fmaxf(X1, X2);
+                        const float yl0 = fminf(Y0, Y1), yh0 = fmaxf(Y0, Y1), yl1 = fminf(Y1, Y2), yh1 = fmaxf(Y1, Y2);
+                        a00 = fmaf(fmaxf(fminf(xh0, yh0) - fmaxf(xl0, yl0), 0.0f), qb, a00);
+                        a01 = fmaf(fmaxf(fminf(xh1, yh0) - fmaxf(xl1, yl0), 0.0f), qb, a01);
+                        a10 = fmaf(fmaxf(fminf(xh0, yh1) - fmaxf(xl0, yl1), 0.0f), qb, a10);
+                        a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
                     }
                 }
             }
-            fout[sd.img0 + ((long long)i * L + r) * L + c] = acc;
+            float *__restrict__ fo = fout + sd.img0 + (long long)i * L * L;
+            fo[(long long)r * L + c] = a00;
+            if (c + 1 < L) fo[(long long)r * L + c + 1] = a01;
+            if (r + 1 < L) {
+                fo[(long long)(r + 1) * L + c] = a10;
+                if (c + 1 < L) fo[(long long)(r + 1) * L + c + 1] = a11;
+            }
         }
         if (partials != nullptr) {
-            const double tot = block_sum_256(inside ? (double)acc * (double)acc : 0.0, sh);
+            double sq = 0.0;
+            if (any) {
+                sq = (double)a00 * (double)a00;
+                if (c + 1 < L) sq += (double)a01 * (double)a01;
+                if (r + 1 < L) {
+                    sq += (double)a10 * (double)a10;
+                    if (c + 1 < L) sq += (double)a11 * (double)a11;
+                }
+            }
+            const double tot = block_sum_256(sq, sh);
             if (threadIdx.x == 0) partials[sd.gp0 + (long long)i * sd.nbp + tcy * nt + tcx] = tot;
         }
     }
