@@ -434,6 +434,8 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     }
     if ((st = make_stage(E, E.st_fp, cfp, kCUs * 8, kfp)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8, kbp)) != TNLM_OK) return st;
+    E.st_fp.cu_runs = 1;
+    E.st_bp.cu_runs = 1;
     if ((st = make_stage(E, E.st_vec, cvec, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_reg, creg, kCUs * 4)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_ffilt, cff, kCUs * 8)) != TNLM_OK) return st;
@@ -735,7 +737,7 @@ static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
         int xb[9];
         for (int x = 0; x <= 8; ++x) xb[x] = (int)((long long)d.nrb * x / 8);
         HIP_TRY(hipMemcpy(xbd + 9 * c, xb, sizeof(xb), hipMemcpyHostToDevice));
-        Stage sg{pre + 2 * c, xbd + 9 * c, d.nrb, std::max(1, std::min(d.nrb, kCUs * 4))};
+        Stage sg{pre + 2 * c, xbd + 9 * c, d.nrb, std::max(1, std::min(d.nrb, kCUs * 4)), 0};
         if (sg.grid >= 8) sg.grid -= sg.grid % 8;
         float *o = c == 0 ? o8 : o4;
         hipEvent_t a, b;

@@ -39,6 +39,7 @@ struct Stage {
     const int *xb;    // device [9]: work items [xb[x], xb[x+1]) go to XCD x
     int total;        // pre[ns]
     int grid;         // persistent grid size
+    int cu_runs = 0;  // 1: blocks sharing a CU take consecutive work items
 };
 
 struct Batch {
@@ -105,7 +106,12 @@ __device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stri
     }
     const int x = (int)blockIdx.x % nx;
     const int per_x = (g - x + nx - 1) / nx;          // blocks on this XCD
-    const int k = (int)blockIdx.x / nx;                // rank within the XCD
+    int k = (int)blockIdx.x / nx;                      // rank within the XCD
+    // the blocks of an XCD are spread over its 32 CUs in turn: on request,
+    // give the blocks that share a CU (ranks j, j + 32, ...) consecutive work
+    // items, whose rays overlap in that CU's L1 (projector pair)
+    constexpr int kCUsPerXCD = 32;
+    if (st.cu_runs && per_x % kCUsPerXCD == 0) k = (k % kCUsPerXCD) * (per_x / kCUsPerXCD) + k / kCUsPerXCD;
     first = load_const(st.xb, x) + k;
     stride = per_x;
     count = load_const(st.xb, x + 1);
