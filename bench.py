@@ -115,7 +115,7 @@ def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
     against the learned warm start + batched engine, on 512^2 slices."""
     import synth
     from paper_1009_1351_amd import Recon
-    from paper_1009_1351_amd.warmstart import WarmStartNet, solve_learned
+    from paper_1009_1351_amd.warmstart import LearnedSolver, WarmStartNet
     net = WarmStartNet(phases=10, base=32)
     net.load_weights(WEIGHTS)
     cases = [synth.make_case("C5eval", slice_index=20_000 + k) for k in range(n_slices)]
@@ -124,19 +124,20 @@ def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
     ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(dev) for c in cases]
     ws = [torch.from_numpy(np.asarray(c.w, np.float32)).to(dev) for c in cases]
     plain = [Recon.from_geometry(c.geom, max_outer=c0.max_outer, tol=tol, device=dev, **prm) for c in cases]
-    plain[0].solve(ys[0], ws[0])   # warm-up
-    solve_learned([c.geom for c in cases[:1]], ys[:1], ws[:1], net, tol=tol, max_outer=c0.max_outer,
-                  restart_after=restart_after, device=dev, **prm)
+    solver = LearnedSolver([c.geom for c in cases], net, tol=tol, max_outer=c0.max_outer, restart_after=restart_after,
+                           device=dev, **prm)
+    plain[0].solve(ys[0], ws[0])   # warm-up of both paths
+    solver.solve(ys, ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = [rc.solve(y, w) for rc, y, w in zip(plain, ys, ws)]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, it_l, st_l, used = solve_learned([c.geom for c in cases], ys, ws, net, tol=tol, max_outer=c0.max_outer,
-                                        restart_after=restart_after, device=dev, **prm)
+    _, it_l, st_l, used = solver.solve(ys, ws)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
+    solver.close()
     return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, h_rel 0.6, "
                         f"to relative update {tol} (cap {c0.max_outer})",
             "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters": [r[1] for r in res],
@@ -235,7 +236,28 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
     json.dump(tj, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
 
 
+def summarize_bf16(kt_dir, command):
+    """profiles/regularize_bf16_c2_batch.md: FP32 and BF16-MFMA regulariser
+    kernels of one traced run of both bench legs."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = [r for r in csv.DictReader(open(f)) if kind_of(r["Name"]) in ("regularize", "regularize_bf16")]
+    out = ["# Regulariser: FP32 box sums against BF16 MFMA patch distances, C2 batch", "",
+           "Command (repository root):", "", "    " + command, "",
+           "| kernel | calls | avg us |", "|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} |")
+    avg = {kind_of(r["Name"]): float(r["AverageNs"]) for r in rows}
+    if "regularize" in avg and "regularize_bf16" in avg:
+        out += ["", f"BF16 MFMA / FP32 time per launch: {avg['regularize_bf16'] / avg['regularize']:.2f}", ""]
+    open(os.path.join(ROOT, "profiles", "regularize_bf16_c2_batch.md"), "w").write("\n".join(out))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-bf16":
+        summarize_bf16(sys.argv[2], sys.argv[3])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize":
         # bench.py summarize KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON "COMMAND" "COUNTERS_COMMAND"
         summarize_profiles(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[6], sys.argv[7], sys.argv[5])
@@ -247,6 +269,7 @@ def main():
     ap.add_argument("--iters", type=int, default=50, help="outer iterations per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and warm-start legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--learned-slices", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
     a = ap.parse_args()
@@ -338,7 +361,7 @@ def main():
         out["bf16_mfma"] = {"value": u / d2, "regularize_ms_per_step": round(tb["regularize"][0], 3),
                             "fp32_regularize_ms_per_step": round(per_kind["regularize"][0] / a.steps, 3)}
         bb.close()
-        if os.path.exists(WEIGHTS):
+        if os.path.exists(WEIGHTS) and not a.no_learned:
             log("learned warm start leg ...")
             out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
         else:

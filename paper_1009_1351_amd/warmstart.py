@@ -195,36 +195,54 @@ def warm_starts(recons, ys, ws, net, batch=4):
     return f_out, used
 
 
-def solve_learned(geoms, ys, ws, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
-    """Learned + batched solve of many slices to a relative-update tolerance.
+class LearnedSolver:
+    """Learned + batched solve of a fixed set of slice geometries to a
+    relative-update tolerance (contexts are built once, at construction).
 
-    Warm starts (warm_starts) for all slices, then one batched solve. A slice
-    still above the tolerance after `restart_after` further iterations (the
-    TNLM outer iteration can settle into a period-2 cycle instead of
-    converging) restarts cold, from the FBP of all phases, in a second batched
-    solve with the remaining iteration budget. Returns (images, iterations
-    per slice counted from the start, statuses, used_warm)."""
-    from .recon import Batch, Recon
-    kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=device)
-    recons = [Recon.from_geometry(g, **kw) for g in geoms]
-    fs, used = warm_starts(recons, ys, ws, net)
-    k1 = max_outer - WARM_START_ITERS if restart_after is None else min(restart_after, max_outer - WARM_START_ITERS)
-    bt = Batch(geoms, init="user", max_outer=k1, tol=tol, **kw)
-    fs, it, _, st, _ = bt.solve(ys, ws, fs)
-    bt.close()
-    iters = [WARM_START_ITERS + k for k in it]
-    redo = [j for j in range(len(geoms)) if st[j] != 0]
-    left = max_outer - WARM_START_ITERS - k1
-    if redo and left > 0:
-        b2 = Batch([geoms[j] for j in redo], init="fbp", max_outer=left, tol=tol, **kw)
-        f2, it2, _, st2, _ = b2.solve([ys[j] for j in redo], [ws[j] for j in redo])
-        b2.close()
-        for t, j in enumerate(redo):
-            fs[j], st[j] = f2[t], st2[t]
-            iters[j] += it2[t]
-    for rc in recons:
-        rc.close()
-    return fs, iters, st, used
+    solve(): warm starts (warm_starts) for all slices, then one batched solve
+    of at most `restart_after` further iterations. A slice still above the
+    tolerance then (the TNLM outer iteration can settle into a period-2 cycle
+    instead of converging) restarts cold, from the FBP of all phases, with
+    the remaining iteration budget, on its own context. Iterations are
+    counted per slice from the first one."""
+
+    def __init__(self, geoms, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
+        from .recon import Batch, Recon
+        self.net, self.n = net, len(geoms)
+        self.k1 = max_outer - WARM_START_ITERS
+        if restart_after is not None:
+            self.k1 = min(restart_after, self.k1)
+        self.left = max_outer - WARM_START_ITERS - self.k1
+        kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=device)
+        self.recons = [Recon.from_geometry(g, max_outer=max(self.left, 1), tol=tol, **kw) for g in geoms]
+        self.batch = Batch(geoms, init="user", max_outer=self.k1, tol=tol, **kw)
+
+    def solve(self, ys, ws):
+        fs, used = warm_starts(self.recons, ys, ws, self.net)
+        fs, it, _, st, _ = self.batch.solve(ys, ws, fs)
+        iters = [WARM_START_ITERS + k for k in it]
+        st = list(st)
+        if self.left > 0:
+            for j in range(self.n):
+                if st[j] != 0:
+                    fj, kj, _, sj = self.recons[j].solve(ys[j], ws[j])
+                    fs[j], st[j] = fj, sj
+                    iters[j] += kj
+        return fs, iters, st, used
+
+    def close(self):
+        self.batch.close()
+        for rc in self.recons:
+            rc.close()
+
+
+def solve_learned(geoms, ys, ws, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
+    """One-shot LearnedSolver(...).solve(ys, ws); returns (images, iterations, statuses, used_warm)."""
+    sol = LearnedSolver(geoms, net, patch=patch, window=window, h=h, mu_hat=mu_hat, tol=tol, max_outer=max_outer,
+                        restart_after=restart_after, device=device)
+    out = sol.solve(ys, ws)
+    sol.close()
+    return out
 
 
 def make_pairs(cases, *, device, chunk=32, tol=1e-4, max_outer=400, patch=7, window=15, log=None):
@@ -278,5 +296,5 @@ def train(net, X, T, *, epochs=4, batch=8, lr=1e-3, lr_final=1e-4, seed=0, log=N
     return hist
 
 
-__all__ = ["WarmStartNet", "warm_starts", "solve_learned", "make_pairs", "train", "data_cost", "rel_change",
+__all__ = ["WarmStartNet", "warm_starts", "LearnedSolver", "solve_learned", "make_pairs", "train", "data_cost", "rel_change",
            "WARM_START_ITERS"]

@@ -121,3 +121,52 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
         monkeypatch.setenv("TNLM_ROWS_PER_LANE", rows)
         o, _, _, _ = recon_for(case.geom, **kw).solve(y, w)
         assert torch.equal(o, ref), rows
+
+
+def test_benchmark_batch_matches_single_slices_and_oracle(orc):
+    """The benchmark's own launch configuration: dose cases a, b, c of the
+    256^2 workload (360/60/60 views x 512 bins, patch 7, window 15) in one
+    batch, with its cost-cut XCD ranges. Two outer iterations equal the
+    single-slice contexts bitwise; the first iteration of dose case c matches
+    the FP64 oracle (whole CGLS output, sampled regulariser outputs)."""
+    from paper_1009_1351_amd import Batch
+    announce("benchmark batch (C2 a/b/c)")
+    cases = [synth.make_case(n, K=2) for n in ("C2a", "C2b", "C2c")]
+    c0 = cases[0]
+    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, max_outer=2)
+    ys = [to_dev(c.y) for c in cases]
+    ws = [to_dev(c.w) for c in cases]
+    bt = Batch([c.geom for c in cases], **kw)
+    fs, iters, _, sts, st = bt.solve(ys, ws)
+    assert st == 0 and iters == [2, 2, 2]
+    for c, y, w, f in zip(cases, ys, ws, fs):
+        rc = recon_for(c.geom, **kw)
+        f1, _, _, _ = rc.solve(y, w)
+        assert torch.equal(f, f1), c.name
+    # dose case c, one iteration, against the oracle
+    c = cases[2]
+    y, w = f32(c.y), f32(c.w)
+    G = orc.Geometry(c.geom)
+    b1 = Batch([c.geom], **{**kw, "max_outer": 1})
+    f_gpu = to_host(b1.solve([to_dev(y)], [to_dev(w)])[0][0])
+    rc = recon_for(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat)
+    f0 = to_host(rc.fbp(to_dev(y)))
+    g = orc.cgls(G, y, w, f0, 3)
+    g_gpu = to_host(rc.data_step(to_dev(y), to_dev(w), to_dev(f0)))
+    assert rel_l2_per_phase(g_gpu, g).max() < 1e-5
+    # regulariser on sampled pixels, from the GPU's own CGLS output (as in the kernel)
+    rng = np.random.default_rng(11)
+    h32, mu32 = float(np.float32(c.h)), float(np.float32(c.mu_hat))
+    d, W, N, L = c.patch, c.window, 10, 256
+    R = W // 2
+    for _ in range(16):
+        i, r, col = int(rng.integers(N)), int(rng.integers(L)), int(rng.integers(L))
+        acc = 0.0
+        for j in ((i - 1) % N, (i + 1) % N):
+            wts, _ = orc.weights(g_gpu[i], g_gpu[j], r, col, d, W, h32)
+            for dy in range(-R, R + 1):
+                for dx in range(-R, R + 1):
+                    if not np.isnan(wts[dy + R, dx + R]):
+                        acc += wts[dy + R, dx + R] * g_gpu[j, r + dy, col + dx]
+        expect = max(g_gpu[i, r, col] / (1 + mu32) + mu32 / (2 * mu32 + 2) * acc, 0.0)
+        assert abs(f_gpu[i, r, col] - expect) <= 1e-5 * max(abs(expect), 1e-3), (i, r, col)
