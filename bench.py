@@ -146,6 +146,65 @@ def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
             "learned_reached_tol": int(sum(s_ == 0 for s_ in st_l)), "speedup": t_plain / t_learned}
 
 
+def batched_legs(torch, dev, n_c3, n_c4, iters=10):
+    """Optional legs on the batched and precision workloads: a ragged batch of
+    n_c3 slices (L from {128..512}, 40-360 views, B = 1.5 L) solved as one
+    batch (graph replay, no per-kernel events) against the same slices solved
+    one at a time; and n_c4 slices at 512^2 (720 bins, 120 views) with the
+    FP32 and the BF16-MFMA regulariser."""
+    import synth
+    from paper_1009_1351_amd import Batch, Recon
+    out = {}
+
+    def arrays(cases):
+        return ([torch.from_numpy(c.y.astype(np.float32)).to(dev) for c in cases],
+                [torch.from_numpy(c.w.astype(np.float32)).to(dev) for c in cases])
+
+    if n_c3:
+        cases = [synth.make_case("C3", slice_index=s, K=iters) for s in range(n_c3)]
+        ys, ws = arrays(cases)
+        kw = dict(patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat, max_outer=iters, tol=0.0, device=dev)
+        units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
+        bt = Batch([c.geom for c in cases], **kw)
+        bt.solve(ys, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.solve(ys, ws)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        bt.close()
+        rcs = [Recon.from_geometry(c.geom, **kw) for c in cases]
+        rcs[0].solve(ys[0], ws[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for rc, y, w in zip(rcs, ys, ws):
+            rc.solve(y, w)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["batched_c3"] = {"slices": n_c3, "iters": iters, "shapes": [[c.geom.L, c.geom.n_views, c.geom.n_bins]
+                                                                        for c in cases],
+                             "batched_value": units / tb, "one_at_a_time_value": units / tp, "unit": "phase-pixel*iters/s"}
+    if n_c4:
+        cases = [synth.make_case("C4", slice_index=s, K=iters) for s in range(n_c4)]
+        ys, ws = arrays(cases)
+        res = {}
+        for mode in ("fp32", "bf16_mfma"):
+            bt = Batch([c.geom for c in cases], patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat,
+                       max_outer=iters, tol=0.0, ssd_mode=mode, device=dev)
+            bt.solve(ys, ws)
+            bt.timing(True)
+            t0 = time.perf_counter()
+            bt.solve(ys, ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t = bt.timing_read()
+            bt.close()
+            units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
+            res[mode] = {"value": units / dt, "regularize_ms_per_launch": t["regularize"][0] / max(t["regularize"][1], 1)}
+        out["precision_c4"] = {"slices": n_c4, "iters": iters, **res}
+    return out
+
+
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
            "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
 
@@ -272,6 +331,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--learned-slices", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
+    ap.add_argument("--c3", type=int, default=0, help="also run a ragged batch of this many slices")
+    ap.add_argument("--c4", type=int, default=0, help="also run this many 512^2 slices with both SSD modes")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -366,6 +427,9 @@ def main():
             out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
         else:
             out["learned_vs_plain"] = None
+    if a.c3 or a.c4:
+        log("batched / precision legs ...")
+        out.update(batched_legs(torch, dev, a.c3, a.c4))
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(lambda n: synth.make_case(n, K=a.iters))

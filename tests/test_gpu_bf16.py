@@ -51,3 +51,48 @@ def test_bf16_trajectory_error_C1(orc):
     err = rel_l2_per_phase(to_host(f), ref)
     announce(f"bf16 C1 trajectory: rel L2 per phase {np.array2string(err, precision=2)}")
     assert k == case.max_outer and err.max() < 5e-3
+
+
+def test_bf16_precision_workload_sampled(orc):
+    """Precision workload shape (10 phases, 512^2, 720 bins, 120 views, I0
+    5e4, patch 7, window 15): one regulariser sweep with BF16-MFMA distances
+    from the CGLS output of the FBP start, against the FP64 oracle's Eq. 7
+    on sampled pixels; per-phase relative L2 and max error are printed."""
+    case = synth.make_case("C4", slice_index=0)
+    y, w = case_inputs(case)
+    kw = dict(patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat)
+    rc32 = recon_for(case.geom, **kw)
+    rc16 = recon_for(case.geom, ssd_mode="bf16_mfma", **kw)
+    yd, wd = to_dev(y), to_dev(w)
+    gd = rc32.data_step(yd, wd, rc32.fbp(yd))
+    g = to_host(gd)
+    out16 = to_host(rc16.regularize(gd, gd, gd))
+    out32 = to_host(rc32.regularize(gd, gd, gd))
+    rng = np.random.default_rng(21)
+    h32, mu32 = float(np.float32(case.h)), float(np.float32(case.mu_hat))
+    d, W, N, L = case.patch, case.window, 10, case.geom.L
+    R = W // 2
+    exp_, got16, got32, ph = [], [], [], []
+    for i in range(N):
+        for _ in range(12):
+            r, c = int(rng.integers(L)), int(rng.integers(L))
+            acc = 0.0
+            for j in ((i - 1) % N, (i + 1) % N):
+                wts, _ = orc.weights(g[i], g[j], r, c, d, W, h32)
+                for dy in range(-R, R + 1):
+                    for dx in range(-R, R + 1):
+                        if not np.isnan(wts[dy + R, dx + R]):
+                            acc += wts[dy + R, dx + R] * g[j, r + dy, c + dx]
+            exp_.append(max(g[i, r, c] / (1 + mu32) + mu32 / (2 * mu32 + 2) * acc, 0.0))
+            got16.append(out16[i, r, c])
+            got32.append(out32[i, r, c])
+            ph.append(i)
+    exp_, got16, got32, ph = map(np.asarray, (exp_, got16, got32, ph))
+    rel16 = [np.linalg.norm(got16[ph == i] - exp_[ph == i]) / np.linalg.norm(exp_[ph == i]) for i in range(N)]
+    mx16 = [np.abs(got16[ph == i] - exp_[ph == i]).max() / np.abs(exp_).max() for i in range(N)]
+    rel32 = [np.linalg.norm(got32[ph == i] - exp_[ph == i]) / np.linalg.norm(exp_[ph == i]) for i in range(N)]
+    announce("bf16 precision workload, sampled rel L2 per phase: " + " ".join(f"{e:.1e}" for e in rel16))
+    announce("bf16 precision workload, sampled max abs / max per phase: " + " ".join(f"{e:.1e}" for e in mx16))
+    announce("fp32 on the same samples, rel L2 per phase: " + " ".join(f"{e:.1e}" for e in rel32))
+    assert max(rel32) < 1e-5
+    assert max(rel16) < 1e-3
