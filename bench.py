@@ -335,8 +335,8 @@ def main():
     ap.add_argument("--c4", type=int, default=0, help="also run this many 512^2 slices with both SSD modes")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(slices shard across GPUs without communication, see the design notes)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(slices would shard across GPUs without communication)"}))
         sys.exit(2)
 
     import torch

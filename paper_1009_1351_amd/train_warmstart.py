@@ -1,4 +1,4 @@
-"""Train and evaluate the learned warm start (command-line driver).
+"""Train and evaluate the learned warm start (command-line tool).
 
     python -m paper_1009_1351_amd.train_warmstart --pairs 2000 --out net.ckpt
     python -m paper_1009_1351_amd.train_warmstart --eval-only --ckpt net.ckpt
