@@ -297,3 +297,31 @@ def test_C2a_one_iteration_sampled(orc):
                         acc += wts[dy + R, dx + R] * g[j, r + dy, c + dx]
         expect = max(g[i, r, c] / (1 + mu32) + mu32 / (2 * mu32 + 2) * acc, 0.0)
         assert abs(out[i, r, c] - expect) <= 1e-5 * max(abs(expect), 1e-3), (i, r, c)
+
+
+# -------------------------------------------------------------- maximum sizes
+def test_projector_pair_at_maximum_sizes(orc):
+    """The largest image side and bin count the boundary accepts (L = B = 4096;
+    one phase, two views): P and P^T against the oracle, and the adjoint
+    identity in FP64 sums."""
+    announce("projector pair at L = B = 4096")
+    geom = synth.ScanGeometry(n_phases=1, L=4096, n_views=2, n_bins=4096)
+    rc = recon_for(geom, patch=3, window=5)
+    f = synth.configs.random_images((1, 4096, 4096), 105)
+    q = synth.configs.random_images((1, 2, 4096), 106, 0.0, 1.0)
+    G = orc.Geometry(geom)
+    # Bars: each FP32 matrix entry is a difference of plane parameters of up to
+    # ~350 mm (rounded to ~3e-5 mm) over 0.12 mm pixels, a relative error of
+    # ~2.5e-4 per entry. A ray sums ~8000 entries, so P averages it down (bar
+    # 2e-5, measured 3.7e-6); with two views a pixel of P^T sums 2-3 entries
+    # (bar 1e-3, measured 2.9e-4). The adjoint identity checks that both use
+    # the same entries.
+    qg = to_host(rc.project(to_dev(f)))
+    e_p = rel_l2_per_phase(qg, orc.project(G, f32(f))).max()
+    fg = to_host(rc.backproject(to_dev(q)))
+    e_b = rel_l2_per_phase(fg, orc.backproject(G, f32(q))).max()
+    announce(f"L = B = 4096: rel L2 P {e_p:.2e}, P^T {e_b:.2e}")
+    assert e_p < 2e-5 and e_b < 1e-3
+    lhs = float(np.sum(qg * f32(q)))
+    rhs = float(np.sum(f32(f) * fg))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
