@@ -182,14 +182,20 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
 
     const float *TG = nsel ? tg1 : tg0;
     const float *TV = nsel ? tv1 : tv0;
-    const int dy0 = half == 0 ? -R : 1, dy1 = half == 0 ? 0 : R;
     const int ta = 2 * l16 + R;
     const int trb = band * kBY + R;
     const float nk = a.nk;
     const int yb = y0 + band * kBY;
 
-    for (int dy = dy0; dy <= dy1; ++dy) {
-        for (int dx = -R; dx <= R; ++dx) {
+    // offsets nearest the centre first (rows 0, -1, ..., -R for one half and
+    // 1, ..., R for the other; columns 0, 1, -1, 2, -2, ...): the smallest
+    // distance, usually near the centre, is met early and later offsets
+    // rarely rescale the running sums
+    const int nrow = half == 0 ? R + 1 : R;
+    for (int kr = 0; kr < nrow; ++kr) {
+        const int dy = half == 0 ? -kr : kr + 1;
+        for (int kc = 0; kc <= 2 * R; ++kc) {
+            const int dx = (kc & 1) ? (kc + 1) >> 1 : -(kc >> 1);
             float ha[NR], hb[NR];
             const float *rowp = TG + (trb + dy) * TCW + ta + dx;
 #pragma unroll
