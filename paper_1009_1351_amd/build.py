@@ -49,7 +49,26 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    _build_capi_test(verbose)
     return LIB
+
+
+def _build_capi_test(verbose: bool) -> None:
+    """The C program of tests/capi, compiled as plain C against the header and
+    linked to the in-tree library (it checks that the boundary is C)."""
+    root = os.path.dirname(HERE)
+    src = os.path.join(root, "tests", "capi", "solve_c.c")
+    if not os.path.exists(src):
+        return
+    exe = os.path.join(root, "tests", "capi", "solve_c")
+    cmd = ["gcc", "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I" + os.path.join(root, "include"), src, "-o", exe, "-L" + HERE, "-ltnlm",
+           "-Wl,-rpath," + HERE, "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C test program failed to build:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", exe)
 
 
 if __name__ == "__main__":
