@@ -205,6 +205,33 @@ def batched_legs(torch, dev, n_c3, n_c4, iters=10):
     return out
 
 
+def omega_star_leg(torch, dev, iters=50):
+    """Adaptive weights against fixed weights from the phantom (the method's
+    ideal-weight reference) on the three 256^2 dose cases: relative L2 error
+    to the phantom after `iters` outer iterations, and that of the FBP start."""
+    import synth
+    from paper_1009_1351_amd import Recon
+    out = {}
+    for n in ("C2a", "C2b", "C2c"):
+        c = synth.make_case(n, K=iters)
+        y = torch.from_numpy(c.y.astype(np.float32)).to(dev)
+        w = torch.from_numpy(c.w.astype(np.float32)).to(dev)
+        truth = torch.from_numpy(c.truth.astype(np.float32)).to(dev)
+        rc = Recon.from_geometry(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat, max_outer=iters)
+
+        def err(f):
+            return float(torch.linalg.vector_norm(f - truth) / torch.linalg.vector_norm(truth))
+        e_fbp = err(rc.fbp(y))
+        fa, _, _, _ = rc.solve(y, w)
+        e_a = err(fa)
+        rc.set_guide(truth)
+        fs, _, _, _ = rc.solve(y, w)
+        e_s = err(fs)
+        rc.set_guide(None)
+        out[n] = {"fbp_all": e_fbp, "adaptive": e_a, "fixed_from_phantom": e_s}
+    return {"iters": iters, "rel_l2_error_to_phantom": out}
+
+
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
            "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
 
@@ -333,6 +360,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
     ap.add_argument("--c3", type=int, default=0, help="also run a ragged batch of this many slices")
     ap.add_argument("--c4", type=int, default=0, help="also run this many 512^2 slices with both SSD modes")
+    ap.add_argument("--omega-star", action="store_true", help="also compare adaptive and phantom-derived weights")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
@@ -427,6 +455,9 @@ def main():
             out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
         else:
             out["learned_vs_plain"] = None
+    if a.omega_star:
+        log("fixed-weight reference ...")
+        out["omega_star"] = omega_star_leg(torch, dev)
     if a.c3 or a.c4:
         log("batched / precision legs ...")
         out.update(batched_legs(torch, dev, a.c3, a.c4))

@@ -218,6 +218,16 @@ tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches)
 tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, double *out);
 
 /*
+ * Fixed weights (Eq. 3 with a given image): from now on tnlm_step and
+ * tnlm_solve take the patch weights of every Gauss-Jacobi sweep from d_guide
+ * ([N][L][L] float32 device, caller-owned, read during those calls) instead
+ * of from the data-step output g^(k); NULL restores the adaptive weights.
+ * With the ground truth as guide this is the ideal-weight reference of the
+ * method. Synchronises.
+ */
+tnlm_status tnlm_set_guide(tnlm_ctx *ctx, const float *d_guide);
+
+/*
  * Relative change between two image stacks of the context's slice, as used by
  * the stop rule of the TNLM algorithm box: out = ||a - b|| / max(||a||, 1e-30)
  * over all phases (double sums, fixed order). Returns TNLM_E_NONFINITE if

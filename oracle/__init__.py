@@ -39,7 +39,8 @@ class _Geom(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("patch", C.c_int32), ("window", C.c_int32), ("h", C.c_double), ("mu_hat", C.c_double),
                 ("beta", C.c_double), ("m1_cgls", C.c_int32), ("m2_jacobi", C.c_int32),
-                ("max_outer", C.c_int32), ("tol_rel_update", C.c_double)]
+                ("max_outer", C.c_int32), ("tol_rel_update", C.c_double),
+                ("guide", C.POINTER(C.c_double))]   # NULL: weights from g^(k); else fixed weights (Eq. 3)
 
 
 _lib = None
@@ -61,7 +62,7 @@ def lib():
             ("orc_weights", [C.c_int, C.c_int, C.c_int, C.c_double, D, D, C.c_int, C.c_int, D, D], None),
             ("orc_regularize", [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, D, D, D, D,
                                 C.c_int], None),
-            ("orc_gauss_jacobi", [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, D, D],
+            ("orc_gauss_jacobi", [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, D, D, D],
              None),
             ("orc_step", [G, P, D, D, D], C.c_double),
             ("orc_solve", [G, P, D, D, D, C.c_int, D, D], C.c_int),
@@ -101,8 +102,16 @@ def _geom(g) -> Geometry:
     return g if isinstance(g, Geometry) else Geometry(g)
 
 
-def params(patch=5, window=11, h=0.02, mu_hat=1.0, beta=1.0, m1=3, m2=1, max_outer=10, tol=0.0) -> _Params:
-    return _Params(patch, window, h, mu_hat, beta, m1, m2, max_outer, tol)
+def params(patch=5, window=11, h=0.02, mu_hat=1.0, beta=1.0, m1=3, m2=1, max_outer=10, tol=0.0,
+           guide=None) -> _Params:
+    """guide: None, or an [N][L][L] stack from which the weights are taken in
+    every outer iteration instead of from the data-step output (Eq. 3 with a
+    fixed image, e.g. the ground truth)."""
+    p = _Params(patch, window, h, mu_hat, beta, m1, m2, max_outer, tol, None)
+    if guide is not None:
+        p._guide = np.ascontiguousarray(guide, dtype=np.float64)   # kept alive with the struct
+        p.guide = _d(p._guide)
+    return p
 
 
 def case_params(case, **over) -> _Params:
@@ -169,11 +178,12 @@ def regularize(guide, value, g, patch, window, h, mu_hat, clamp=True) -> np.ndar
     return out
 
 
-def gauss_jacobi(g, patch, window, h, mu_hat, m2=1) -> np.ndarray:
+def gauss_jacobi(g, patch, window, h, mu_hat, m2=1, guide=None) -> np.ndarray:
     g = _arr(g)
     N, L = g.shape[0], g.shape[-1]
     out = np.empty_like(g)
-    lib().orc_gauss_jacobi(N, L, patch, window, h, mu_hat, m2, _d(g), _d(out))
+    gd = None if guide is None else _arr(guide)
+    lib().orc_gauss_jacobi(N, L, patch, window, h, mu_hat, m2, _d(g), None if gd is None else _d(gd), _d(out))
     return out
 
 

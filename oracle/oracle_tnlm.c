@@ -62,6 +62,7 @@ typedef struct {
     double h, mu_hat, beta;
     int32_t m1_cgls, m2_jacobi, max_outer;
     double tol_rel_update;
+    const double *guide; /* NULL: weights from g^(k); else fixed weights from this [N][L][L] stack (Eq. 3) */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -447,14 +448,15 @@ void orc_regularize(int N, int L, int d, int W, double h, double mu_hat, const d
     }
 }
 
-/* M2 Gauss-Jacobi sweeps from u0 = g with weights frozen from g; then f = max(u, 0). */
+/* M2 Gauss-Jacobi sweeps from u0 = g with weights frozen from the guide
+ * stack (g itself when guide is NULL); then f = max(u, 0). */
 void orc_gauss_jacobi(int N, int L, int d, int W, double h, double mu_hat, int m2, const double *g,
-                      double *f) {
+                      const double *guide, double *f) {
     const size_t n = (size_t)N * L * L;
     double *u = (double *)malloc(sizeof(double) * n), *un = (double *)malloc(sizeof(double) * n);
     memcpy(u, g, sizeof(double) * n);
     for (int m = 0; m < m2; m++) {
-        orc_regularize(N, L, d, W, h, mu_hat, g, u, g, un, 0);
+        orc_regularize(N, L, d, W, h, mu_hat, guide ? guide : g, u, g, un, 0);
         memcpy(u, un, sizeof(double) * n);
     }
     for (size_t k = 0; k < n; k++) f[k] = u[k] > 0.0 ? u[k] : 0.0;
@@ -470,7 +472,7 @@ double orc_step(const orc_geom *g, const orc_params *p, const double *y, const d
     const size_t n = (size_t)g->n_phases * g->L * g->L;
     double *gk = (double *)malloc(sizeof(double) * n), *fn = (double *)malloc(sizeof(double) * n);
     orc_cgls(g, y, w, f, p->m1_cgls, p->beta, gk);                                   /* step 2 */
-    orc_gauss_jacobi(g->n_phases, g->L, p->patch, p->window, p->h, p->mu_hat, p->m2_jacobi, gk,
+    orc_gauss_jacobi(g->n_phases, g->L, p->patch, p->window, p->h, p->mu_hat, p->m2_jacobi, gk, p->guide,
                      fn); /* steps 3-5 */
     double dd = 0.0, nn = 0.0;
     for (size_t k = 0; k < n; k++) {

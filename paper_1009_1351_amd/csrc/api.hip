@@ -68,6 +68,7 @@ struct Engine {
     float *hfilt = nullptr, *cw = nullptr;
     Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{}, st_tr{};
     float *fT = nullptr;   // transposed copy of the image a projection reads
+    const float *fixed_guide = nullptr;   // caller's weight guide for every iteration (null: g^(k))
     struct StageSpec {
         Stage *st;
         std::vector<int> counts;
@@ -508,6 +509,7 @@ static void enqueue_data_step(Engine *E, const Batch &bt, const float *y, const 
 // Gauss-Jacobi sweeps from g = u, weights from u; last sweep writes f (clamped)
 static void enqueue_regularize(Engine *E, const Batch &bt, float *f, bool record) {
     const float *g = E->cb.u;
+    const float *guide = E->fixed_guide ? E->fixed_guide : g;
     const int M2 = E->prm.m2_jacobi;
     const float *val = g;
     for (int m = 0; m < M2; ++m) {
@@ -515,11 +517,11 @@ static void enqueue_regularize(Engine *E, const Batch &bt, float *f, bool record
         float *dst = last ? f : ((m & 1) ? E->ub : E->ua);
         if (E->prm.ssd_mode == TNLM_SSD_BF16_MFMA)
             TIMED(E, K_REGULARIZE,
-                  launch_regularize_mfma(bt, E->st_reg, E->rp, g, val, g, dst, last ? 1 : 0,
+                  launch_regularize_mfma(bt, E->st_reg, E->rp, guide, val, g, dst, last ? 1 : 0,
                                          last && record ? E->relpart : nullptr, E->nonfinite(), E->cur));
         else
             TIMED(E, K_REGULARIZE,
-                  launch_regularize(bt, E->st_reg, E->rp, E->rows_per_lane, g, val, g, dst, last ? 1 : 0,
+                  launch_regularize(bt, E->st_reg, E->rp, E->rows_per_lane, guide, val, g, dst, last ? 1 : 0,
                                     last && record ? E->relpart : nullptr, E->nonfinite(), E->cur));
         val = dst;
     }
@@ -937,6 +939,15 @@ extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const flo
     for (double v : part) s += v;
     *out = s;
     return last_launch();
+}
+
+extern "C" tnlm_status tnlm_set_guide(tnlm_ctx *ctx, const float *d_guide) {
+    CHECK_CTX();
+    Engine *E = &ctx->e;
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    if (E->fixed_guide != d_guide) E->drop_graph();   // the captured iteration reads the guide pointer
+    E->fixed_guide = d_guide;
+    return TNLM_OK;
 }
 
 extern "C" tnlm_status tnlm_rel_change(tnlm_ctx *ctx, const float *d_a, const float *d_b, double *out) {

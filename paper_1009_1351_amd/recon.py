@@ -143,6 +143,13 @@ class Recon:
         check(nat.lib.tnlm_autotune(self._ctx, C.byref(rpl), ms))
         return rpl.value, (ms[0], ms[1])
 
+    def set_guide(self, guide=None):
+        """Fixed weights from `guide` ([N][L][L] float32 on the device) for
+        step/solve, or None for the adaptive weights. The tensor must stay
+        alive while it is set."""
+        self._guide = guide
+        check(nat.lib.tnlm_set_guide(self._ctx, None if guide is None else self._img(guide, "guide")))
+
     def history(self):
         n = self.params["max_outer"]
         buf = (C.c_float * n)()

@@ -225,6 +225,31 @@ def test_trajectory_C1_matches_oracle(orc, m2):
     np.testing.assert_allclose(rc.history(), hist, rtol=1e-3)
 
 
+def test_fixed_guide_trajectory_matches_oracle(orc):
+    """Weights from a fixed image (the phantom) in every iteration, through
+    tnlm_set_guide, against the oracle with the same guide; clearing the guide
+    restores the adaptive trajectory."""
+    case = synth.make_case("C1")
+    y, w = case_inputs(case)
+    truth = f32(case.truth)
+    prm = orc.case_params(case, h=float(np.float32(case.h)), mu_hat=float(np.float32(case.mu_hat)), guide=truth)
+    ref, _, _, _ = orc.solve(orc.Geometry(case.geom), prm, y, w)
+    rc = recon_for(case.geom, patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat,
+                   max_outer=case.max_outer)
+    td = to_dev(truth)
+    rc.set_guide(td)
+    f, k, _, _ = rc.solve(to_dev(y), to_dev(w))
+    err = rel_l2_per_phase(to_host(f), ref)
+    announce(f"fixed guide C1: rel L2 per phase max {err.max():.2e}")
+    assert k == case.max_outer and err.max() < 1e-4
+    rc.set_guide(None)
+    f2, _, _, _ = rc.solve(to_dev(y), to_dev(w))
+    rc2 = recon_for(case.geom, patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat,
+                    max_outer=case.max_outer)
+    f3, _, _, _ = rc2.solve(to_dev(y), to_dev(w))
+    assert torch.equal(f2, f3)
+
+
 def test_solve_is_deterministic_and_resumable():
     case = synth.make_case("C1", K=6)
     y, w = to_dev(case.y), to_dev(case.w)

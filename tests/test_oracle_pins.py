@@ -459,3 +459,27 @@ def test_cost_decreases_each_outer_iteration_C1(orc):
         data, reg = orc.cost(G, prm, case.y, case.w, f, g)
         costs.append(data + case.mu_hat * beta / 2 * reg)
     assert all(b < a for a, b in zip(costs, costs[1:])), costs
+
+
+def test_fixed_guide_of_constant_image_gives_window_means():
+    """Weights taken from a fixed guide (Eq. 3 with a given image): for a
+    constant guide every patch distance is 0, so each weight is 1 over the
+    window truncated to the image, and one Gauss-Jacobi sweep of Eq. 7 is the
+    plain window mean of the neighbour phases (computed here directly)."""
+    import oracle
+    N, L, d, W, mu = 4, 13, 3, 5, 0.7
+    rng = np.random.default_rng(31)
+    g = rng.uniform(0.0, 0.03, size=(N, L, L))
+    guide = np.full((N, L, L), 0.0123)
+    out = oracle.gauss_jacobi(g, d, W, 0.01, mu, m2=1, guide=guide)
+    R = W // 2
+    expect = np.empty_like(g)
+    for i in range(N):
+        for r in range(L):
+            for c in range(L):
+                rs, cs = slice(max(r - R, 0), min(r + R, L - 1) + 1), slice(max(c - R, 0), min(c + R, L - 1) + 1)
+                m = g[(i - 1) % N][rs, cs].mean() + g[(i + 1) % N][rs, cs].mean()
+                expect[i, r, c] = max(g[i, r, c] / (1 + mu) + mu / (2 * mu + 2) * m, 0.0)
+    np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-15)
+    # and the weights from g itself differ (the guide is really used)
+    assert np.abs(oracle.gauss_jacobi(g, d, W, 0.01, mu, m2=1) - expect).max() > 1e-6
