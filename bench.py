@@ -232,6 +232,29 @@ def omega_star_leg(torch, dev, iters=50):
     return {"iters": iters, "rel_l2_error_to_phantom": out}
 
 
+def quality_leg(torch, dev, iters=50):
+    """Image quality of the three 256^2 dose cases in the layout of the
+    paper's tables: mean over phases of the CNR of the two regions (Eq. 10)
+    and of the SNR (Eq. 11), for FBP of each phase's own views, FBP of all
+    phases' views, and TNLM after `iters` outer iterations."""
+    import synth
+    from synth import quality
+    from paper_1009_1351_amd import Recon
+    out = {}
+    for n in ("C2a", "C2b", "C2c"):
+        c = synth.make_case(n, K=iters)
+        y = torch.from_numpy(c.y.astype(np.float32)).to(dev)
+        w = torch.from_numpy(c.w.astype(np.float32)).to(dev)
+        rc = Recon.from_geometry(c.geom, patch=c.patch, window=c.window, h=c.h, mu_hat=c.mu_hat, max_outer=iters)
+        host = lambda t: t.cpu().numpy().astype(np.float64)   # noqa: E731
+        f_ph = host(rc.fbp(y, all_phases=False))
+        f_all = host(rc.fbp(y, all_phases=True))
+        f_tnlm = host(rc.solve(y, w)[0])
+        out[n] = {"fbp_per_phase": quality.report(f_ph, c), "fbp_all_phases": quality.report(f_all, c),
+                  "tnlm": quality.report(f_tnlm, c)}
+    return {"iters": iters, "cases": out}
+
+
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
            "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
 
@@ -361,6 +384,7 @@ def main():
     ap.add_argument("--c3", type=int, default=0, help="also run a ragged batch of this many slices")
     ap.add_argument("--c4", type=int, default=0, help="also run this many 512^2 slices with both SSD modes")
     ap.add_argument("--omega-star", action="store_true", help="also compare adaptive and phantom-derived weights")
+    ap.add_argument("--quality", action="store_true", help="also report CNR and SNR of FBP and TNLM images")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
@@ -455,6 +479,9 @@ def main():
             out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
         else:
             out["learned_vs_plain"] = None
+    if a.quality:
+        log("image quality ...")
+        out["quality"] = quality_leg(torch, dev)
     if a.omega_star:
         log("fixed-weight reference ...")
         out["omega_star"] = omega_star_leg(torch, dev)

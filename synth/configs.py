@@ -65,6 +65,7 @@ class Case:
     m2: int
     max_outer: int
     tol: float
+    ellipses: list = None   # per phase: the phantom's ellipses (for regions of interest)
 
 
 CONFIGS = {
@@ -125,7 +126,7 @@ def make_case(config: str = "C1", slice_index: int = 0, n_phases: int = 10, *, L
         y[i], w[i] = noisy_measurement(pbar[i], I0, rng, law=law)
     return Case(name=f"{config}/s{slice_index}", geom=geom, truth=truth, y=y, w=w, I0=I0, patch=patch,
                 window=window, h=h_from_rel(h_rel, patch), mu_hat=mu_hat, beta=beta, m1=m1, m2=m2,
-                max_outer=K, tol=tol)
+                max_outer=K, tol=tol, ellipses=phases)
 
 
 def random_images(shape, seed: int, lo: float = 0.0, hi: float = 0.03) -> np.ndarray:
