@@ -170,3 +170,22 @@ def test_benchmark_batch_matches_single_slices_and_oracle(orc):
                         acc += wts[dy + R, dx + R] * g_gpu[j, r + dy, col + dx]
         expect = max(g_gpu[i, r, col] / (1 + mu32) + mu32 / (2 * mu32 + 2) * acc, 0.0)
         assert abs(f_gpu[i, r, col] - expect) <= 1e-5 * max(abs(expect), 1e-3), (i, r, col)
+
+
+def test_batched_workload_shapes_equal_single_slices():
+    """Slices of the batched workload at their real shapes (L 128 / 384 / 256 /
+    512, 48-230 views, B = 1.5 L), mixed in one batch: each equals its
+    single-slice solve bitwise after two outer iterations."""
+    from paper_1009_1351_amd import Batch
+    announce("batched workload shapes")
+    idx = [6, 4, 8, 3]   # 128 x 48 views, 384 x 61, 256 x 109, 512 x 230
+    cases = [synth.make_case("C3", slice_index=s, K=2) for s in idx]
+    c0 = cases[0]
+    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, max_outer=2)
+    ys = [to_dev(c.y) for c in cases]
+    ws = [to_dev(c.w) for c in cases]
+    fs, iters, _, _, st = Batch([c.geom for c in cases], **kw).solve(ys, ws)
+    assert st == 0 and iters == [2] * len(cases)
+    for c, y, w, f in zip(cases, ys, ws, fs):
+        f1, _, _, _ = recon_for(c.geom, **kw).solve(y, w)
+        assert torch.equal(f, f1), c.name
