@@ -138,12 +138,24 @@ def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     solver.close()
+    from paper_1009_1351_amd.multigrid import MultigridSolver
+    mg = MultigridSolver([c.geom for c in cases], tol=tol, max_outer=c0.max_outer, restart_after=restart_after,
+                         device=dev, **prm)
+    mg.solve(ys, ws)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it_m, it_mc, st_m = mg.solve(ys, ws)
+    torch.cuda.synchronize()
+    t_mg = time.perf_counter() - t0
+    mg.close()
     return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, h_rel 0.6, "
                         f"to relative update {tol} (cap {c0.max_outer})",
             "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters": [r[1] for r in res],
             "learned_batched_wall_s_per_slice": t_learned / n_slices, "learned_iters": it_l,
             "warm_start_used": int(sum(used)), "plain_reached_tol": int(sum(r[3] == 0 for r in res)),
-            "learned_reached_tol": int(sum(s_ == 0 for s_ in st_l)), "speedup": t_plain / t_learned}
+            "learned_reached_tol": int(sum(s_ == 0 for s_ in st_l)), "speedup": t_plain / t_learned,
+            "multigrid_wall_s_per_slice": t_mg / n_slices, "multigrid_iters": it_m, "multigrid_coarse_iters": it_mc,
+            "multigrid_reached_tol": int(sum(s_ == 0 for s_ in st_m)), "multigrid_speedup": t_plain / t_mg}
 
 
 def batched_legs(torch, dev, n_c3, n_c4, iters=10):

@@ -263,6 +263,13 @@ tnlm_status tnlm_cnn_forward(tnlm_cnn *net, const float *d_in, float *d_out, int
  * one pixel size serve slices at a finer one. Async. */
 tnlm_status tnlm_cnn_forward_resampled(tnlm_cnn *net, const float *d_in, float *d_out, int32_t n, int32_t H,
                                        int32_t W, int32_t factor);
+/* Bilinear upsampling of n images [n][h][w] -> [n][h*factor][w*factor]
+ * (float32 device; output pixel X samples the input at (X + 1/2)/factor - 1/2,
+ * clamped to the first and last pixel), e.g. a coarse-grid reconstruction as
+ * the start of a fine one. Independent of any context; enqueued on `stream`
+ * (hipStream_t as void*). Async. Errors: tnlm_cnn_last_error(). */
+tnlm_status tnlm_image_upsample(const float *d_in, float *d_out, int32_t n, int32_t h, int32_t w, int32_t factor,
+                                void *stream);
 /* MSE loss (in input_scale units) and its gradient (host_grad nullable, num_params floats). Synchronises. */
 tnlm_status tnlm_cnn_loss_grad(tnlm_cnn *net, const float *d_in, const float *d_target, int32_t n, int32_t H, int32_t W,
                                double *loss, float *host_grad, int64_t ngrad);

@@ -474,6 +474,16 @@ tnlm_status tnlm_cnn_forward_resampled(tnlm_cnn *c, const float *d_in, float *d_
     return TNLM_OK;
 }
 
+tnlm_status tnlm_image_upsample(const float *d_in, float *d_out, int32_t n, int32_t h, int32_t w, int32_t factor,
+                                void *stream) {
+    if (!d_in || !d_out) return cfail(TNLM_E_INVALID_ARG, "null device pointer");
+    if (n < 1 || h < 1 || w < 1 || factor < 1 || factor > 16) return cfail(TNLM_E_SHAPE, "bad image count or size");
+    if ((long long)n * h * w * factor * factor > (1LL << 31)) return cfail(TNLM_E_SHAPE, "output too large");
+    cnn_bilinear_up(d_in, d_out, (size_t)n, h, w, factor, (hipStream_t)stream);
+    CHIP(hipGetLastError());
+    return TNLM_OK;
+}
+
 tnlm_status tnlm_cnn_loss_grad(tnlm_cnn *c, const float *d_in, const float *d_target, int32_t n, int32_t H, int32_t W,
                                double *loss, float *host_grad, int64_t ngrad) {
     tnlm_status s = check_shape(c, n, H, W);

@@ -1,0 +1,82 @@
+"""Coarse-to-fine start of the TNLM solve (the multi-grid speed-up that §4
+proposes; Python face of tnlm_image_upsample plus the batch engine).
+
+Each slice is first solved on the grid with half the side -- pixels twice as
+large over the same field, the same views, bins and measured data -- to a
+looser relative-update tolerance; the bilinear upsampling of that solution is
+the start of the solve at full resolution. As with the learned start, a slice
+still above the tolerance after `restart_after` full-resolution iterations
+restarts from the FBP of all phases. All arithmetic runs in the library's
+kernels; this module orchestrates.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _native as nat
+from ._native import check_cnn
+from .recon import Batch, Recon, _norm_device
+
+
+def upsample(images, factor=2, out=None):
+    """Bilinear upsampling of a [n][h][w] float32 device tensor by `factor`."""
+    n, h, w = images.shape
+    if images.dtype != torch.float32 or not images.is_contiguous() or images.device.type != "cuda":
+        raise ValueError("images must be a contiguous float32 CUDA tensor [n][h][w]")
+    out = torch.empty((n, h * factor, w * factor), dtype=torch.float32, device=images.device) if out is None else out
+    with torch.cuda.device(images.device):
+        stream = torch.cuda.current_stream(images.device).cuda_stream
+        check_cnn(nat.lib.tnlm_image_upsample(C.c_void_p(images.data_ptr()), C.c_void_p(out.data_ptr()), n, h, w,
+                                              int(factor), C.c_void_p(stream)))
+    return out
+
+
+def coarse_geometry(geom):
+    """The same scan on a grid with half the side (L must be even)."""
+    if geom.L % 2:
+        raise ValueError("the image side must be even for a coarse level")
+    return dataclasses.replace(geom, L=geom.L // 2)
+
+
+class MultigridSolver:
+    """Coarse-to-fine solve of a fixed set of slice geometries to a
+    relative-update tolerance (contexts built once, at construction).
+    solve() returns (images, full-resolution iterations, coarse iterations,
+    statuses); the full-resolution count includes a cold restart's."""
+
+    def __init__(self, geoms, *, patch, window, h, mu_hat, tol, max_outer, coarse_tol=1e-3, coarse_max=200,
+                 restart_after=None, device=None):
+        self.device = _norm_device(device)
+        self.n = len(geoms)
+        kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=self.device)
+        self.k1 = max_outer if restart_after is None else min(restart_after, max_outer)
+        self.left = max_outer - self.k1
+        self.coarse = Batch([coarse_geometry(g) for g in geoms], init="fbp", max_outer=coarse_max, tol=coarse_tol,
+                            **kw)
+        self.fine = Batch(geoms, init="user", max_outer=self.k1, tol=tol, **kw)
+        self.recons = [Recon.from_geometry(g, max_outer=max(self.left, 1), tol=tol, **kw) for g in geoms]
+
+    def solve(self, ys, ws):
+        fc, itc, _, _, _ = self.coarse.solve(ys, ws)
+        f0 = [upsample(f) for f in fc]
+        fs, it, _, st, _ = self.fine.solve(ys, ws, f0)
+        iters, st = list(it), list(st)
+        if self.left > 0:
+            for j in range(self.n):
+                if st[j] != 0:
+                    fj, kj, _, sj = self.recons[j].solve(ys[j], ws[j])
+                    fs[j], st[j] = fj, sj
+                    iters[j] += kj
+        return fs, iters, list(itc), st
+
+    def close(self):
+        self.coarse.close()
+        self.fine.close()
+        for rc in self.recons:
+            rc.close()
+
+
+__all__ = ["upsample", "coarse_geometry", "MultigridSolver"]
