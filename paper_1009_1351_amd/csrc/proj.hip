@@ -243,23 +243,36 @@ __device__ __forceinline__ float fan_atan(float t) {
 // planes c, c+1, c+2 (and r, r+1, r+2) are evaluated once and take the lo or
 // hi role of each pixel by the signs.
 template <bool XP, bool YP>
+__device__ __forceinline__ void bp_block_ray(const float4 A, const float qb, float fc0, float fr0, float &a00,
+                                             float &a01, float &a10, float &a11) {
+    const float fc1 = fc0 + 1.0f, fc2 = fc0 + 2.0f, fr1 = fr0 + 1.0f, fr2 = fr0 + 2.0f;
+    const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
+    const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
+    const float xl0 = XP ? X0 : X1, xh0 = XP ? X1 : X0;   // column c
+    const float xl1 = XP ? X1 : X2, xh1 = XP ? X2 : X1;   // column c + 1
+    const float yl0 = YP ? Y0 : Y1, yh0 = YP ? Y1 : Y0;   // row r
+    const float yl1 = YP ? Y1 : Y2, yh1 = YP ? Y2 : Y1;   // row r + 1
+    a00 = fmaf(fmaxf(fminf(xh0, yh0) - fmaxf(xl0, yl0), 0.0f), qb, a00);
+    a01 = fmaf(fmaxf(fminf(xh1, yh0) - fmaxf(xl1, yl0), 0.0f), qb, a01);
+    a10 = fmaf(fmaxf(fminf(xh0, yh1) - fmaxf(xl0, yl1), 0.0f), qb, a10);
+    a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
+}
+
+// Two candidates per pass, both requested before either is used. On an odd
+// count the last pass reads candidate b1 twice and adds its second copy with
+// weight 0 (a finite segment times +0 leaves every sum unchanged), so the
+// additions happen in the same order as one candidate per pass.
+template <bool XP, bool YP>
 __device__ __forceinline__ void bp_block_oriented(const float4 *__restrict__ Av, const float *__restrict__ qv, int b0,
                                                   int b1, float fc0, float fr0, float &a00, float &a01, float &a10,
                                                   float &a11) {
-    const float fc1 = fc0 + 1.0f, fc2 = fc0 + 2.0f, fr1 = fr0 + 1.0f, fr2 = fr0 + 2.0f;
-    for (int b = b0; b <= b1; ++b) {
-        const float4 A = Av[b];
-        const float qb = qv[b];
-        const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
-        const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
-        const float xl0 = XP ? X0 : X1, xh0 = XP ? X1 : X0;   // column c
-        const float xl1 = XP ? X1 : X2, xh1 = XP ? X2 : X1;   // column c + 1
-        const float yl0 = YP ? Y0 : Y1, yh0 = YP ? Y1 : Y0;   // row r
-        const float yl1 = YP ? Y1 : Y2, yh1 = YP ? Y2 : Y1;   // row r + 1
-        a00 = fmaf(fmaxf(fminf(xh0, yh0) - fmaxf(xl0, yl0), 0.0f), qb, a00);
-        a01 = fmaf(fmaxf(fminf(xh1, yh0) - fmaxf(xl1, yl0), 0.0f), qb, a01);
-        a10 = fmaf(fmaxf(fminf(xh0, yh1) - fmaxf(xl0, yl1), 0.0f), qb, a10);
-        a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
+    for (int b = b0; b <= b1; b += 2) {
+        const int bn = min(b + 1, b1);
+        const float4 A = Av[b], An = Av[bn];
+        const float qb = qv[b], qr = qv[bn];
+        const float qn = b + 1 <= b1 ? qr : 0.0f;
+        bp_block_ray<XP, YP>(A, qb, fc0, fr0, a00, a01, a10, a11);
+        bp_block_ray<XP, YP>(An, qn, fc0, fr0, a00, a01, a10, a11);
     }
 }
 
