@@ -14,7 +14,8 @@ Metric: phase-pixel*iterations per second = sum over slices of N*L^2*K / wall
 seconds. Also reported: the same workload with BF16-MFMA patch distances,
 and -- when trained warm-start weights are present -- wall seconds per
 10-phase slice to a relative update of 1e-4 for the learned warm start +
-batched engine against the plain path (cold start, one slice at a time).
+batched engine and for the coarse-to-fine start, against the plain path
+(cold start, one slice at a time).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -329,8 +330,8 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
     cw = copy_bytes / 1024 / max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
     out = ["# HBM traffic per dispatch, C2 batch", "",
            "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two counter runs:", "",
-           "    " + counters_command.replace("COUNTER", "FETCH_SIZE"),
-           "    " + counters_command.replace("COUNTER", "WRITE_SIZE"), "",
+           "    " + counters_command.replace("COUNTER", "FETCH_SIZE").replace("DIR", "fetch"),
+           "    " + counters_command.replace("COUNTER", "WRITE_SIZE").replace("DIR", "write"), "",
            f"Calibration: a 256 MiB device-to-device copy in the same runs reads as "
            f"{copy_bytes / 1024 / cf:.1f} KiB fetched and {copy_bytes / 1024 / cw:.1f} KiB written, "
            f"so fetch counts are scaled by {cf:.4f} and write counts by {cw:.4f}.", "",
@@ -381,6 +382,7 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize":
         # bench.py summarize KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON "COMMAND" "COUNTERS_COMMAND"
+        # (COUNTERS_COMMAND with COUNTER and DIR standing for the counter and its output folder)
         summarize_profiles(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[6], sys.argv[7], sys.argv[5])
         return
     ap = argparse.ArgumentParser()
