@@ -180,8 +180,11 @@ tnlm_status tnlm_timing_read(tnlm_ctx *ctx, double *ms /* [TNLM_KIND_COUNT] */,
  * JSON-lines cache (env TNLM_AUTOTUNE_CACHE, default
  * $HOME/.cache/tnlm_autotune.jsonl) keyed by (patch, window, L rounded up to
  * a power of two); later contexts of that class start from the cached
- * choice. rows_per_lane (nullable) receives the choice, ms (nullable, 2
- * floats) the kernel times of the 8- and 4-row candidates. Synchronises.
+ * choice. A context (or batch) with FP32 distances whose class has no cached
+ * choice runs this tuning once at creation; env TNLM_ROWS_PER_LANE (4 or 8)
+ * forces a height and skips it. rows_per_lane (nullable) receives the choice,
+ * ms (nullable, 2 floats) the kernel times of the 8- and 4-row candidates.
+ * Synchronises.
  */
 tnlm_status tnlm_autotune(tnlm_ctx *ctx, int32_t *rows_per_lane, float *ms);
 

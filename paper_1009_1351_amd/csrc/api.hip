@@ -322,6 +322,7 @@ static tnlm_status make_stage(Engine &E, Stage &st, const std::vector<int> &coun
 }
 
 static int autotuned_rows_per_lane(const tnlm_params &p, int L);
+static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out);
 
 static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, const tnlm_params *params,
                                void *stream) {
@@ -340,8 +341,12 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     E.prm = *params;
     E.ns = ns;
     E.rp = RegParams{params->patch, params->window, params->h, params->mu_hat};
+    // tile height: forced by TNLM_ROWS_PER_LANE, else the cached choice for
+    // this (patch, window, L) class, else tuned at the end of the set-up
     const char *env_rpl = std::getenv("TNLM_ROWS_PER_LANE");
-    E.rows_per_lane = env_rpl ? (std::atoi(env_rpl) == 4 ? 4 : 8) : autotuned_rows_per_lane(*params, geoms[0].L);
+    const int cached_rpl = env_rpl ? (std::atoi(env_rpl) == 4 ? 4 : 8) : autotuned_rows_per_lane(*params, geoms[0].L);
+    E.rows_per_lane = cached_rpl ? cached_rpl : 8;
+    const bool tune_now = cached_rpl == 0 && params->ssd_mode == TNLM_SSD_FP32;
     const char *env_graph = std::getenv("TNLM_NO_GRAPH");
     E.use_graph = !(env_graph && env_graph[0] == '1');
 
@@ -470,6 +475,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     HIP_TRY(hipMemset(E.flags, 0, 4 * ns * sizeof(int)));
     HIP_TRY(hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipDeviceSynchronize());
+    if (tune_now) return engine_autotune(&E, nullptr, nullptr);
     return TNLM_OK;
 }
 
@@ -691,7 +697,7 @@ static std::string tune_key(const tnlm_params &p, int L) {
 static int autotuned_rows_per_lane(const tnlm_params &p, int L) {
     std::ifstream in(tune_cache_path());
     std::string line, key = "\"" + tune_key(p, L) + "\"";
-    int v = 8;
+    int v = 0;   // no entry
     while (std::getline(in, line)) {
         if (line.find(key) == std::string::npos) continue;
         const size_t k = line.find("\"rows_per_lane\":");

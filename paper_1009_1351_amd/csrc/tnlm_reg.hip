@@ -64,10 +64,10 @@ __device__ __forceinline__ float rowsum(float x) {
 }
 
 // Patch-row sums for the lane's two columns xa = base + 2l (value ea) and
-// xb = xa + 1 (value eb): ha = sum of E over columns xa-S..xa+S, hb over xb-S..xb+S.
+// xb = xa + 1 (value eb), given p = ea + eb: ha = sum of E over columns
+// xa-S..xa+S, hb over xb-S..xb+S.
 template <int S>
-__device__ __forceinline__ void hsum(float ea, float eb, float &ha, float &hb) {
-    const float p = ea + eb;
+__device__ __forceinline__ void hsum(float ea, float eb, float p, float &ha, float &hb) {
     if constexpr (S % 2 == 1) {
         constexpr int H = (S - 1) / 2;
         const float qs = rowsum<-H, H>(p);
@@ -107,13 +107,17 @@ __device__ __forceinline__ void merge(float nk, float Dm1, float num1, float den
     const float m = fminf(Dm, Dm1);
     const float s0 = __builtin_amdgcn_exp2f((Dm - m) * nk);
     const float s1 = __builtin_amdgcn_exp2f((Dm1 - m) * nk);
-    num = num * s0 + num1 * s1;
-    den = den * s0 + den1 * s1;
+    num = fmaf(num, s0, num1 * s1);
+    den = fmaf(den, s0, den1 * s1);
     Dm = m;
 }
 
 template <int S, int kBY>
 __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs a) {
+    // no implicit multiply-add fusion: whether the compiler fuses would differ
+    // between instances of this template, and with it the rounding; every
+    // fused operation is written out, so all tile heights give the same bits
+#pragma clang fp contract(off)
     extern __shared__ float lds[];
     __shared__ double shred[kBlock];
     constexpr int TW = 32 - 2 * S, TH = 4 * kBY, NR = kBY + 2 * S;
@@ -200,11 +204,10 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
             const float *rowp = TG + (trb + dy) * TCW + ta + dx;
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
-                float ea = gia[k] - rowp[k * TCW];
-                float eb = gib[k] - rowp[k * TCW + 1];
-                ea *= ea;
-                eb *= eb;
-                hsum<S>(ea, eb, ha[k], hb[k]);
+                const float da = gia[k] - rowp[k * TCW];
+                const float db = gib[k] - rowp[k * TCW + 1];
+                const float eb = db * db;
+                hsum<S>(da * da, eb, fmaf(da, da, eb), ha[k], hb[k]);
             }
             const bool ca = va && (unsigned)(xa + dx) < (unsigned)L;
             const bool cb = vb && (unsigned)(xa + 1 + dx) < (unsigned)L;
@@ -278,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
                 if (a.clamp) u = fmaxf(u, 0.0f);
                 if (a.relpart) {
                     const double df = (double)u - (double)oi[e];
-                    dd += df * df;
-                    nn += (double)u * (double)u;
+                    dd = fma(df, df, dd);
+                    nn = fma((double)u, (double)u, nn);
                 }
                 bad |= !isfinite(u);
                 oi[e] = u;
@@ -290,8 +293,8 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
                 if (a.clamp) u = fmaxf(u, 0.0f);
                 if (a.relpart) {
                     const double df = (double)u - (double)oi[e];
-                    dd += df * df;
-                    nn += (double)u * (double)u;
+                    dd = fma(df, df, dd);
+                    nn = fma((double)u, (double)u, nn);
                 }
                 bad |= !isfinite(u);
                 oi[e] = u;

@@ -189,3 +189,22 @@ def test_batched_workload_shapes_equal_single_slices():
     for c, y, w, f in zip(cases, ys, ws, fs):
         f1, _, _, _ = recon_for(c.geom, **kw).solve(y, w)
         assert torch.equal(f, f1), c.name
+
+
+@pytest.mark.parametrize("N,L,d,W,same", [(4, 29, 3, 5, False), (3, 40, 3, 5, True), (3, 40, 5, 11, True),
+                                          (2, 50, 9, 21, True), (5, 70, 7, 15, True)])
+def test_tile_heights_agree_bitwise(monkeypatch, N, L, d, W, same):
+    """Each pixel's arithmetic does not depend on the regulariser's tile height
+    (4 or 8 output rows per lane), so the autotuner may pick either."""
+    announce(f"tile heights N={N} L={L} d={d} W={W}")
+    g = synth.configs.smooth_random_images((N, L, L), 200 + L, passes=1)
+    v = g if same else synth.configs.random_images((N, L, L), 300 + L)
+    gd, vd = to_dev(g), to_dev(v)
+    outs = []
+    for rows in ("8", "4"):
+        monkeypatch.setenv("TNLM_ROWS_PER_LANE", rows)
+        rc = recon_for(synth.ScanGeometry(n_phases=N, L=L, n_views=8, n_bins=16), patch=d, window=W, h=0.004,
+                       mu_hat=0.7)
+        outs.append(rc.regularize(gd, gd if same else vd, gd, clamp=False))
+    assert torch.equal(outs[0], outs[1])
+
