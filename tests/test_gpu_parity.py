@@ -67,6 +67,34 @@ def test_backproject_matches_oracle(orc, shape):
     assert rel_l2_per_phase(f, ref).max() < 2e-6
 
 
+# smallest accepted sizes: one phase, a 3 x 3 image (window 3), one view, one
+# bin; a wide field so that the few rays cross the image
+TINY = [(1, 3, 1, 1), (2, 5, 2, 3), (1, 4, 3, 7), (3, 6, 1, 2)]
+
+
+@pytest.mark.parametrize("shape", TINY)
+def test_tiny_geometries_match_oracle(orc, shape):
+    N, L, V, B = shape
+    announce(f"tiny geometry N={N} L={L} V={V} B={B}")
+    geom = synth.ScanGeometry(n_phases=N, L=L, n_views=V, n_bins=B, fov_mm=300.0)
+    G = orc.Geometry(geom)
+    f = f32(np.random.default_rng(L).uniform(0.01, 0.03, size=(N, L, L)))
+    rc = recon_for(geom, patch=3, window=3, h=0.02, mu_hat=0.5, max_outer=3, tol=0.0)
+    q = to_host(rc.project(to_dev(f)))
+    ref = orc.project(G, f)
+    np.testing.assert_allclose(q, ref, rtol=2e-6, atol=1e-6 * np.abs(ref).max())
+    bq = to_host(rc.backproject(to_dev(ref)))
+    bref = orc.backproject(G, f32(ref))
+    np.testing.assert_allclose(bq, bref, rtol=2e-6, atol=1e-6 * np.abs(bref).max())
+    y = f32(ref)
+    w = np.ones_like(y)
+    out, k, rel, status = rc.solve(to_dev(y), to_dev(w))
+    prm = orc.params(patch=3, window=3, h=float(np.float32(0.02)), mu_hat=0.5, max_outer=3)
+    oref, kr, relr, hist = orc.solve(G, prm, y, w)
+    assert k == kr == 3 and status == 0
+    assert rel_l2_per_phase(to_host(out), oref).max() < 1e-4
+
+
 def test_adjoint_on_gpu():
     geom = small_geom(3, 56, 48, 80)
     rng = np.random.default_rng(103)
