@@ -159,9 +159,10 @@ def main():
         log(f"saved {a.out}")
         del X, T
         torch.cuda.empty_cache()
-    ev = [synth.make_case("C5eval", slice_index=10_000 + k, L=a.eval_L, B=a.eval_B) for k in range(a.eval_slices)]
-    log("evaluation ...")
-    report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after)
+    if a.eval_slices > 0:
+        ev = [synth.make_case("C5eval", slice_index=10_000 + k, L=a.eval_L, B=a.eval_B) for k in range(a.eval_slices)]
+        log("evaluation ...")
+        report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after)
     print(json.dumps(report), flush=True)
 
 
