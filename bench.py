@@ -173,8 +173,16 @@ def batched_legs(torch, dev, n_c3, n_c4, iters=10):
         return ([torch.from_numpy(c.y.astype(np.float32)).to(dev) for c in cases],
                 [torch.from_numpy(c.w.astype(np.float32)).to(dev) for c in cases])
 
+    def make(name, n):
+        cases = []
+        for s in range(n):
+            cases.append(synth.make_case(name, slice_index=s, K=iters))
+            if (s + 1) % 8 == 0 or s + 1 == n:
+                log(f"{name}: {s + 1}/{n} slices generated")
+        return cases
+
     if n_c3:
-        cases = [synth.make_case("C3", slice_index=s, K=iters) for s in range(n_c3)]
+        cases = make("C3", n_c3)
         ys, ws = arrays(cases)
         kw = dict(patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat, max_outer=iters, tol=0.0, device=dev)
         units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
@@ -194,11 +202,12 @@ def batched_legs(torch, dev, n_c3, n_c4, iters=10):
             rc.solve(y, w)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
+        log(f"C3: batched {tb:.2f} s, one at a time {tp:.2f} s")
         out["batched_c3"] = {"slices": n_c3, "iters": iters, "shapes": [[c.geom.L, c.geom.n_views, c.geom.n_bins]
                                                                         for c in cases],
                              "batched_value": units / tb, "one_at_a_time_value": units / tp, "unit": "phase-pixel*iters/s"}
     if n_c4:
-        cases = [synth.make_case("C4", slice_index=s, K=iters) for s in range(n_c4)]
+        cases = make("C4", n_c4)
         ys, ws = arrays(cases)
         res = {}
         for mode in ("fp32", "bf16_mfma"):
