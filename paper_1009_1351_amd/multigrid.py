@@ -3,8 +3,10 @@ proposes; Python face of tnlm_image_upsample plus the batch engine).
 
 Each slice is first solved on the grid with half the side -- pixels twice as
 large over the same field, the same views, bins and measured data -- to a
-looser relative-update tolerance; the bilinear upsampling of that solution is
-the start of the solve at full resolution. As with the learned start, a slice
+looser relative-update tolerance, for at most coarse_max iterations (a coarse
+solve that settles into the period-2 cycle of the outer iteration stops
+there); the bilinear upsampling of that solution is the start of the solve
+at full resolution. As with the learned start, a slice
 still above the tolerance after `restart_after` full-resolution iterations
 restarts from the FBP of all phases. All arithmetic runs in the library's
 kernels; this module orchestrates.
@@ -47,7 +49,7 @@ class MultigridSolver:
     solve() returns (images, full-resolution iterations, coarse iterations,
     statuses); the full-resolution count includes a cold restart's."""
 
-    def __init__(self, geoms, *, patch, window, h, mu_hat, tol, max_outer, coarse_tol=1e-3, coarse_max=200,
+    def __init__(self, geoms, *, patch, window, h, mu_hat, tol, max_outer, coarse_tol=1e-3, coarse_max=50,
                  restart_after=None, device=None):
         self.device = _norm_device(device)
         self.n = len(geoms)

@@ -32,10 +32,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=600, restart_after=64):
+def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=600, restart_after=64, coarse_max=50):
     """Plain (one slice at a time, cold start) against learned + batched
     (warm starts, one batched solve, cold restart of slices still above the
-    tolerance after restart_after iterations), on the same slices."""
+    tolerance after restart_after iterations) and against the coarse-to-fine
+    start (same restart rule), on the same slices."""
     from paper_1009_1351_amd.recon import Batch, Recon
     from paper_1009_1351_amd.warmstart import LearnedSolver
     c0 = cases[0]
@@ -74,6 +75,17 @@ def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=600, restart_after=64
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     solver.close()
+    # coarse-to-fine start (half-resolution solve, upsampled), same restart rule
+    from paper_1009_1351_amd.multigrid import MultigridSolver
+    mg = MultigridSolver(geoms, tol=tol, max_outer=max_outer, restart_after=restart_after, coarse_max=coarse_max,
+                         device=dev, **prm)
+    mg.solve(ys, ws)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fm, it_m, it_mc, st_m = mg.solve(ys, ws)
+    torch.cuda.synchronize()
+    t_mg = time.perf_counter() - t0
+    mg.close()
     diff = [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(fl, fp)]
     err_p = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fp, cases)]
     err_l = [float(np.linalg.norm(f.cpu().numpy() - c.truth) / np.linalg.norm(c.truth)) for f, c in zip(fl, cases)]
@@ -90,6 +102,8 @@ def eval_warm_vs_cold(net, cases, dev, tol=1e-4, max_outer=600, restart_after=64
         "batched_cold": arm(it_c, st_c, t_cold),
         "learned_batched": {**arm(it_l, st_l, t_learned), "warm_used": int(sum(used))},
         "speedup_learned_batched_vs_plain": t_plain / t_learned,
+        "coarse_to_fine": {**arm(it_m, st_m, t_mg), "coarse_max": coarse_max, "coarse_iters_mean": float(np.mean(it_mc)),
+                           "speedup_vs_plain": t_plain / t_mg},
         "on_slices_reaching_tol_in_both": {"count": len(both),
                                            "plain_iters_mean": float(np.mean([it_p[j] for j in both])) if both else None,
                                            "learned_iters_mean": float(np.mean([it_l[j] for j in both])) if both else None},
@@ -115,6 +129,7 @@ def main():
     ap.add_argument("--eval-B", type=int, default=720)
     ap.add_argument("--eval-max-outer", type=int, default=600)
     ap.add_argument("--restart-after", type=int, default=64)
+    ap.add_argument("--coarse-max", type=int, default=50, help="iteration cap of the coarse level (coarse-to-fine arm)")
     ap.add_argument("--out", default="warmstart.ckpt")
     ap.add_argument("--ckpt", default=None)
     ap.add_argument("--eval-only", action="store_true")
@@ -162,7 +177,8 @@ def main():
     if a.eval_slices > 0:
         ev = [synth.make_case("C5eval", slice_index=10_000 + k, L=a.eval_L, B=a.eval_B) for k in range(a.eval_slices)]
         log("evaluation ...")
-        report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after)
+        report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after,
+                                           coarse_max=a.coarse_max)
     print(json.dumps(report), flush=True)
 
 
