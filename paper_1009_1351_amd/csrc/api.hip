@@ -217,9 +217,12 @@ static tnlm_status validate_params(const tnlm_params *p, int minL) {
 }
 
 // Per-ray plane tables in double precision, rounded once to float.
+// crossings receives the slice's ray-pixel crossings (|dc| + |dr| + 1 cells
+// per ray that meets the image), the cost of one forward projection.
 static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
                           std::vector<float4> &vt, std::vector<int4> &vo, std::vector<float> &hf,
-                          std::vector<float> &cw) {
+                          std::vector<float> &cw, double &crossings) {
+    crossings = 0.0;
     const int N = g.n_phases, V = g.n_views, B = g.n_bins, L = g.L;
     const double D = g.pixel_mm, X0 = -0.5 * D * L;
     for (int i = 0; i < N; ++i)
@@ -237,6 +240,11 @@ static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std:
                 rt0.push_back(make_float4((float)(D * ix), (float)((X0 - ox) * ix), (float)(D * iy),
                                           (float)((X0 - oy) * iy)));
                 rt1.push_back(make_float4((float)ox, (float)oy, (float)ux, (float)uy));
+                const double ax = (X0 - ox) * ix, bxp = (X0 + D * L - ox) * ix;
+                const double ay = (X0 - oy) * iy, byp = (X0 + D * L - oy) * iy;
+                const double chord = std::min(std::max(ax, bxp), std::max(ay, byp)) -
+                                     std::max(std::min(ax, bxp), std::min(ay, byp));
+                if (chord > 0.0) crossings += chord * (std::fabs(ux) + std::fabs(uy)) / D + 1.0;
             }
             // orientation of the view's rays: the sign of Ax (and Ay) is that of
             // bin 0 below bin bx (by) and the opposite from there on; the fan is
@@ -354,6 +362,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     std::vector<int4> vo;
     std::vector<float> hf, cw;
     E.geoms.assign(geoms, geoms + ns);
+    std::vector<double> crossings(ns, 0.0);
     E.angles.resize(ns);
     E.sl.resize(ns);
     long long ray = 0, view = 0, img = 0, sino = 0;
@@ -377,7 +386,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         d.sino0 = sino;
         d.hf0 = (int)hf.size();
         d.cw0 = (int)cw.size();
-        if (!append_tables(E.geoms[s], rt0, rt1, vt, vo, hf, cw))
+        if (!append_tables(E.geoms[s], rt0, rt1, vt, vo, hf, cw, crossings[s]))
             return fail(TNLM_E_INVALID_ARG, "ray directions change sign more than once across the fan");
         d.nbp = bp_blocks(d) / d.N;
         d.npp = proj_blocks(d) / d.N;
@@ -426,10 +435,12 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         cfp.push_back(proj_blocks(d));
         cbp.push_back(bp_blocks(d));
         ctr.push_back(tr_blocks(d));
-        // cost models: a projector block walks 256 rays of ~1.2 L cells; a
+        // cost models: a projector block walks its rays' crossings (the
+        // slice's crossings over its blocks: ray lengths and the share of a
+        // slice's last bin block that holds rays differ between slices); a
         // back-projector tile runs V views of a ~40-operation set-up plus
         // ~14 operations per candidate bin, ~1.5 + B D / (fan * SAD) bins
-        kfp.push_back((double)d.L);
+        kfp.push_back(crossings[&d - E.sl.data()] / std::max(1, proj_blocks(d)));
         const double cand = 1.5 + d.B * (double)d.D / (d.B * (double)d.dgamma * 541.0);
         kbp.push_back(d.V * (40.0 + 14.0 * cand));
         cvec.push_back(d.N * vec_blocks(d));
