@@ -221,6 +221,19 @@ tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches)
 tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, double *out);
 
 /*
+ * Both terms of the cost of Eq. 1 for an image stack d_f ([N][L][L]):
+ * out_data as tnlm_data_cost, out_reg = sum_i sum_{j = i-1, i+1} sum_x
+ * sum_y w_ij(x, y) (f_i(x) - f_j(y))^2 over the search window inside the
+ * image, with the normalised weights of Eq. 8 taken from d_guide ([N][L][L],
+ * e.g. the data-step output g^(k)); the cost is out_data + mu_hat beta / 2
+ * out_reg. Device arrays are caller-owned float32, results double on the
+ * host. A diagnostic (direct patch sums, not the solve's kernels).
+ * Synchronises.
+ */
+tnlm_status tnlm_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f, const float *d_guide,
+                      double *out_data, double *out_reg);
+
+/*
  * Fixed weights (Eq. 3 with a given image): from now on tnlm_step and
  * tnlm_solve take the patch weights of every Gauss-Jacobi sweep from d_guide
  * ([N][L][L] float32 device, caller-owned, read during those calls) instead

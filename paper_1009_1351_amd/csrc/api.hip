@@ -958,6 +958,25 @@ extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const flo
     return last_launch();
 }
 
+extern "C" tnlm_status tnlm_cost(tnlm_ctx *ctx, const float *d_y, const float *d_w, const float *d_f,
+                                 const float *d_guide, double *out_data, double *out_reg) {
+    CHECK_CTX();
+    if (!d_y || !d_w || !d_f || !d_guide || !out_data || !out_reg) return fail(TNLM_E_INVALID_ARG, "null pointer");
+    tnlm_status s = tnlm_data_cost(ctx, d_y, d_w, d_f, out_data);
+    if (s != TNLM_OK) return s;
+    Engine *E = &ctx->e;
+    const SliceDesc &d = E->sl[0];
+    const int nb = launch_reg_cost(d.N, d.L, E->prm.patch, E->prm.window, E->prm.h, d_guide, d_f, E->cost_part, 1024,
+                                   E->stream);
+    std::vector<double> part(nb);
+    HIP_TRY(hipMemcpyAsync(part.data(), E->cost_part, nb * sizeof(double), hipMemcpyDeviceToHost, E->stream));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    double r = 0.0;
+    for (double v : part) r += v;
+    *out_reg = r;
+    return last_launch();
+}
+
 extern "C" tnlm_status tnlm_set_guide(tnlm_ctx *ctx, const float *d_guide) {
     CHECK_CTX();
     Engine *E = &ctx->e;

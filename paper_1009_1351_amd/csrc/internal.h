@@ -159,6 +159,9 @@ int launch_diff_sq(const float *a, const float *b, size_t n, double *part, int *
 
 // ---- TNLM regulariser (tnlm_reg.hip)
 int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane);
+// regularisation term of Eq. 1 (one slice); returns the number of partial sums in part
+int launch_reg_cost(int N, int L, int patch, int window, float h, const float *guide, const float *f, double *part,
+                    int max_blocks, hipStream_t strm);
 bool reg_supported(int patch, int window);
 void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int rows_per_lane,
                        const float *guide, const float *value, const float *g, float *out, int clamp,

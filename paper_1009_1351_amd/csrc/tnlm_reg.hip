@@ -314,6 +314,63 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
     }   // work items
 }
 
+// Regularisation term of Eq. 1 for one slice: the sum over phases i, both
+// neighbours j = i-1, i+1, pixels x and the window offsets y inside the
+// image of w_ij(x, y) (f_i(x) - f_j(y))^2, with the normalised weights of
+// Eq. 8 from the guide stack (edge-clamped patches, window-minimum shift as
+// a running minimum). Direct patch sums, one lane per (pixel, neighbour): a
+// diagnostic of the cost, not part of a solve. Per-block FP64 sums in part.
+__global__ __launch_bounds__(kBlock) void k_reg_cost(int N, int L, int S, int R, float nk,
+                                                     const float *__restrict__ guide, const float *__restrict__ f,
+                                                     double *__restrict__ part) {
+    __shared__ double sh[kBlock];
+    const long long plane = (long long)L * L, total = 2LL * N * plane;
+    double acc = 0.0;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int side = (int)(t & 1);
+        long long q = t >> 1;
+        const int c = (int)(q % L);
+        q /= L;
+        const int r = (int)(q % L), i = (int)(q / L);
+        const int j = side ? (i + 1) % N : (i - 1 + N) % N;
+        const float *gi = guide + i * plane, *gj = guide + j * plane, *fj = f + j * plane;
+        const float fx = f[i * plane + (long long)r * L + c];
+        float Dm = INFINITY, num = 0.0f, den = 0.0f;
+        for (int dy = -R; dy <= R; ++dy) {
+            const int r2 = r + dy;
+            if (r2 < 0 || r2 >= L) continue;
+            for (int dx = -R; dx <= R; ++dx) {
+                const int c2 = c + dx;
+                if (c2 < 0 || c2 >= L) continue;
+                float D = 0.0f;
+                for (int py = -S; py <= S; ++py) {
+                    const int ra = min(max(r + py, 0), L - 1), rb = min(max(r2 + py, 0), L - 1);
+                    for (int px = -S; px <= S; ++px) {
+                        const int ca = min(max(c + px, 0), L - 1), cb = min(max(c2 + px, 0), L - 1);
+                        const float d = gi[(long long)ra * L + ca] - gj[(long long)rb * L + cb];
+                        D = fmaf(d, d, D);
+                    }
+                }
+                const float e = fx - fj[(long long)r2 * L + c2];
+                online_add(D, e * e, nk, Dm, num, den);
+            }
+        }
+        acc += (double)num / (double)den;
+    }
+    acc = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+int launch_reg_cost(int N, int L, int patch, int window, float h, const float *guide, const float *f, double *part,
+                    int max_blocks, hipStream_t strm) {
+    const long long total = 2LL * N * L * L;
+    const int nb = (int)std::max(1LL, std::min((long long)max_blocks, (total + kBlock - 1) / kBlock));
+    const float nk = (float)(-1.4426950408889634 / ((double)h * (double)h));
+    k_reg_cost<<<nb, kBlock, 0, strm>>>(N, L, patch / 2, window / 2, nk, guide, f, part);
+    return nb;
+}
+
 static int tile_w(int patch) { return 32 - 2 * (patch / 2); }
 
 int reg_blocks(const SliceDesc &s, int patch, int rows_per_lane) {

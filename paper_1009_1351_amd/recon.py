@@ -143,6 +143,14 @@ class Recon:
         check(nat.lib.tnlm_autotune(self._ctx, C.byref(rpl), ms))
         return rpl.value, (ms[0], ms[1])
 
+    def cost(self, y, w, f, guide):
+        """(data term, regularisation term) of Eq. 1 for f, the weights from
+        guide; the cost is data + mu_hat * beta / 2 * reg (tnlm_cost)."""
+        data, reg = C.c_double(), C.c_double()
+        check(nat.lib.tnlm_cost(self._ctx, self._sino(y, "y"), self._sino(w, "w"), self._img(f, "f"),
+                                self._img(guide, "guide"), C.byref(data), C.byref(reg)))
+        return data.value, reg.value
+
     def set_guide(self, guide=None):
         """Fixed weights from `guide` ([N][L][L] float32 on the device) for
         step/solve, or None for the adaptive weights. The tensor must stay

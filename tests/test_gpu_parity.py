@@ -155,6 +155,48 @@ def test_zero_residual_leaves_image_unchanged():
     assert torch.equal(g, fd)
 
 
+# ----------------------------------------------------------------------- cost
+@pytest.mark.parametrize("N,L,d,W", [(3, 24, 3, 5), (2, 20, 5, 7), (4, 18, 3, 9)])
+def test_cost_matches_oracle(orc, N, L, d, W):
+    """Both terms of Eq. 1 (tnlm_cost) against the oracle's cost."""
+    geom = small_geom(N, L, 16, 24)
+    G = orc.Geometry(geom)
+    f = f32(0.02 + 0.01 * synth.configs.smooth_random_images((N, L, L), 400 + L, passes=1))
+    g = f32(0.02 + 0.01 * synth.configs.smooth_random_images((N, L, L), 500 + L, passes=1))
+    y = f32(orc.project(G, 0.02 + 0.01 * synth.configs.smooth_random_images((N, L, L), 600 + L, passes=1)))
+    w = f32(np.random.default_rng(L).uniform(0.5, 2.0, size=y.shape))
+    h = float(np.float32(0.01))
+    rc = recon_for(geom, patch=d, window=W, h=h, mu_hat=0.5)
+    data, reg = rc.cost(to_dev(y), to_dev(w), to_dev(f), to_dev(g))
+    dr, rr = orc.cost(G, orc.params(patch=d, window=W, h=h, mu_hat=0.5), y, w, f, g)
+    announce(f"cost N={N} L={L} d={d} W={W}: data {data:.6e} vs {dr:.6e}, reg {reg:.6e} vs {rr:.6e}")
+    # data term: projection entries carry ~2e-6 relative FP32 error; residuals
+    # P f - y about a third of P f make that ~7e-6 in r and ~1.5e-5 in r^2
+    assert abs(data - dr) <= 5e-5 * dr
+    # regularisation term: FP32 distances and weights, FP64 sums
+    assert abs(reg - rr) <= 1e-4 * rr
+
+
+def test_cost_decreases_each_outer_iteration_C1(orc):
+    """The cost of Eq. 1 (weights from the data-step output) along the GPU
+    trajectory of the 64^2 workload decreases in each outer iteration, as it
+    does along the oracle's."""
+    case = synth.make_case("C1")
+    y, w = case_inputs(case)
+    beta = orc.power_beta(orc.Geometry(case.geom), w, 20)
+    rc = recon_for(case.geom, patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat, beta=beta)
+    yd, wd = to_dev(y), to_dev(w)
+    f = rc.fbp(yd)
+    costs = []
+    for _ in range(6):
+        g = rc.data_step(yd, wd, f)
+        rc.step(yd, wd, f)
+        data, reg = rc.cost(yd, wd, f, g)
+        costs.append(data + case.mu_hat * beta / 2 * reg)
+    announce(f"C1 costs {costs}")
+    assert all(b < a for a, b in zip(costs, costs[1:])), costs
+
+
 # ---------------------------------------------------------------- regulariser
 REG_CASES = [
     # N, L, d, W, h, mu, same guide/value
