@@ -211,6 +211,16 @@ void tnlm_batch_destroy(tnlm_batch *b);
  */
 tnlm_status tnlm_batch_solve(tnlm_batch *b, const float *const *d_y, const float *const *d_w, float *const *d_f,
                              int32_t *out_iters, float *out_rel, tnlm_status *out_status);
+/*
+ * As tnlm_batch_solve for the slices with active[s] != 0 (active: host
+ * [n_slices]); the others take no part: their d_y, d_w, d_f are neither read
+ * nor written (their pointers may be NULL), and they report 0 iterations and
+ * TNLM_OK. With init = TNLM_INIT_USER a slice continues from d_f, so a solve
+ * can resume a subset of a batch (the outer iteration's state is the image).
+ */
+tnlm_status tnlm_batch_solve_active(tnlm_batch *b, const float *const *d_y, const float *const *d_w,
+                                   float *const *d_f, const int32_t *active, int32_t *out_iters, float *out_rel,
+                                   tnlm_status *out_status);
 tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable);
 tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches);
 

@@ -57,6 +57,8 @@ for _name, _args, _res in [
     ("tnlm_batch_destroy", [_P], None),
     ("tnlm_batch_solve", [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(C.c_int32), _FP,
                           C.POINTER(C.c_int)], C.c_int),
+    ("tnlm_batch_solve_active", [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), _FP, C.POINTER(C.c_int)], C.c_int),
     ("tnlm_batch_timing_enable", [_P, C.c_int32], C.c_int),
     ("tnlm_batch_timing_read", [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
     ("tnlm_data_cost", [_P, _P, _P, _P, C.POINTER(C.c_double)], C.c_int),
@@ -89,7 +91,7 @@ for _name, _args, _res in [
 def exported_symbols():
     return ["tnlm_recon_init", "tnlm_destroy", "tnlm_step", "tnlm_solve", "tnlm_get_history", "tnlm_project",
             "tnlm_backproject", "tnlm_fbp", "tnlm_data_step", "tnlm_regularize", "tnlm_timing_enable",
-            "tnlm_timing_read", "tnlm_autotune", "tnlm_batch_init", "tnlm_batch_destroy", "tnlm_batch_solve",
+            "tnlm_timing_read", "tnlm_autotune", "tnlm_batch_init", "tnlm_batch_destroy", "tnlm_batch_solve", "tnlm_batch_solve_active",
             "tnlm_batch_timing_enable", "tnlm_batch_timing_read", "tnlm_data_cost", "tnlm_cost", "tnlm_rel_change", "tnlm_set_guide", "tnlm_image_upsample", "tnlm_cnn_create",
             "tnlm_cnn_destroy", "tnlm_cnn_num_params", "tnlm_cnn_get_params", "tnlm_cnn_set_params",
             "tnlm_cnn_forward", "tnlm_cnn_forward_resampled", "tnlm_cnn_loss_grad", "tnlm_cnn_train_step", "tnlm_cnn_save", "tnlm_cnn_load",

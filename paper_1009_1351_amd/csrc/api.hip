@@ -606,17 +606,39 @@ static tnlm_status restage(Engine *E, const std::vector<char> &active) {
 }
 
 // Full solve on contiguous batch arrays (y, w, f); f holds f^(0) when init is user.
-static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float *f) {
+// active (nullable, [ns]): slices with 0 take no part (marked finished from
+// the start and left out of the work tables; their images are not written)
+static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float *f,
+                                const std::vector<char> *active = nullptr) {
     hipStream_t st = E->stream;
     E->cur = st;
     const int ns = E->ns;
     Batch bt = E->batch;
     launch_fill_int(E->flags, 4 * ns, 0, st);
-    TIMED(E, K_OTHER, launch_check_finite(y, E->nsino, E->nonfinite(), st));
-    TIMED(E, K_OTHER, launch_check_finite(w, E->nsino, E->nonfinite(), st));
+    int ninactive = 0;
+    if (active) {
+        std::vector<int> dn(ns);
+        for (int s = 0; s < ns; ++s) ninactive += (dn[s] = (*active)[s] ? 0 : 1);
+        HIP_TRY(hipMemcpyAsync(E->done(), dn.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));   // dn leaves scope
+    }
+    if (!active) {
+        TIMED(E, K_OTHER, launch_check_finite(y, E->nsino, E->nonfinite(), st));
+        TIMED(E, K_OTHER, launch_check_finite(w, E->nsino, E->nonfinite(), st));
+    } else {   // only the active slices' data (the others' regions may hold anything)
+        for (int s = 0; s < ns; ++s) {
+            if (!(*active)[s]) continue;
+            const SliceDesc &d = E->sl[s];
+            const size_t nsn = (size_t)d.N * d.V * d.B;
+            TIMED(E, K_OTHER, launch_check_finite(y + d.sino0, nsn, E->nonfinite(), st));
+            TIMED(E, K_OTHER, launch_check_finite(w + d.sino0, nsn, E->nonfinite(), st));
+            if (E->prm.init != TNLM_INIT_FBP_ALL)
+                TIMED(E, K_OTHER, launch_check_finite(f + d.img0, (size_t)d.N * d.L * d.L, E->nonfinite(), st));
+        }
+    }
     if (E->prm.init == TNLM_INIT_FBP_ALL)
         TIMED(E, K_FBP, launch_fbp(bt, E->st_ffilt, E->st_fbp_all, y, E->hfilt, E->cw, E->Q, f, 1, st));
-    else
+    else if (!active)
         TIMED(E, K_OTHER, launch_check_finite(f, E->nimg, E->nonfinite(), st));
     if (E->prm.m1_cgls > 0) TIMED(E, K_VECTOR, launch_sqrt(w, E->cb.sw, E->nsino, st));
     std::vector<int> hf(4 * ns, 0);
@@ -633,6 +655,11 @@ static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float
     const int chunk = 8;
     int ndone = 0;   // slices the work tables currently leave out
     tnlm_status rs = TNLM_OK;
+    if (ninactive == ns) return TNLM_OK;
+    if (ninactive > 0 && ns > 1) {
+        if ((rs = restage(E, *active)) != TNLM_OK) return rs;
+        ndone = ninactive;
+    }
     for (int k = 0; k < K; ++k) {
         if (graph) HIP_TRY(hipGraphLaunch(E->gexec, st));
         else enqueue_step(E, bt, y, w, f);
@@ -1075,17 +1102,20 @@ extern "C" tnlm_status tnlm_batch_init(tnlm_batch **out, int32_t n_slices, const
 
 extern "C" void tnlm_batch_destroy(tnlm_batch *b) { delete b; }
 
-extern "C" tnlm_status tnlm_batch_solve(tnlm_batch *bt, const float *const *d_y, const float *const *d_w,
-                                        float *const *d_f, int32_t *out_iters, float *out_rel,
-                                        tnlm_status *out_status) {
+static tnlm_status batch_solve(tnlm_batch *bt, const float *const *d_y, const float *const *d_w, float *const *d_f,
+                               const int32_t *active, int32_t *out_iters, float *out_rel, tnlm_status *out_status) {
     if (!bt) return fail(TNLM_E_INVALID_ARG, "null batch");
     if (!d_y || !d_w || !d_f) return fail(TNLM_E_INVALID_ARG, "null pointer array");
     Engine *E = &bt->e;
+    std::vector<char> act(E->ns, 1);
+    if (active)
+        for (int s = 0; s < E->ns; ++s) act[s] = active[s] != 0;
     for (int s = 0; s < E->ns; ++s)
-        if (!d_y[s] || !d_w[s] || !d_f[s])
+        if (act[s] && (!d_y[s] || !d_w[s] || !d_f[s]))
             return fail(TNLM_E_INVALID_ARG, "null device pointer for slice " + std::to_string(s));
     hipStream_t st = E->stream;
     for (int s = 0; s < E->ns; ++s) {
+        if (!act[s]) continue;
         const SliceDesc &d = E->sl[s];
         const size_t nsn = (size_t)d.N * d.V * d.B, ni = (size_t)d.N * d.L * d.L;
         HIP_TRY(hipMemcpyAsync(E->Y + d.sino0, d_y[s], nsn * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -1093,9 +1123,10 @@ extern "C" tnlm_status tnlm_batch_solve(tnlm_batch *bt, const float *const *d_y,
         if (E->prm.init == TNLM_INIT_USER)
             HIP_TRY(hipMemcpyAsync(E->F + d.img0, d_f[s], ni * sizeof(float), hipMemcpyDeviceToDevice, st));
     }
-    tnlm_status s = engine_solve(E, E->Y, E->Wt, E->F);
+    tnlm_status s = engine_solve(E, E->Y, E->Wt, E->F, active ? &act : nullptr);
     if (s != TNLM_OK) return s;
     for (int k = 0; k < E->ns; ++k) {
+        if (!act[k]) continue;
         const SliceDesc &d = E->sl[k];
         HIP_TRY(hipMemcpyAsync(d_f[k], E->F + d.img0, (size_t)d.N * d.L * d.L * sizeof(float), hipMemcpyDeviceToDevice,
                                st));
@@ -1104,6 +1135,19 @@ extern "C" tnlm_status tnlm_batch_solve(tnlm_batch *bt, const float *const *d_y,
     s = engine_results(E, out_iters, out_rel, out_status);
     if (s < 0) return fail(s, "a slice failed (see out_status)");
     return s;
+}
+
+extern "C" tnlm_status tnlm_batch_solve(tnlm_batch *bt, const float *const *d_y, const float *const *d_w,
+                                        float *const *d_f, int32_t *out_iters, float *out_rel,
+                                        tnlm_status *out_status) {
+    return batch_solve(bt, d_y, d_w, d_f, nullptr, out_iters, out_rel, out_status);
+}
+
+extern "C" tnlm_status tnlm_batch_solve_active(tnlm_batch *bt, const float *const *d_y, const float *const *d_w,
+                                               float *const *d_f, const int32_t *active, int32_t *out_iters,
+                                               float *out_rel, tnlm_status *out_status) {
+    if (!active) return fail(TNLM_E_INVALID_ARG, "null active mask");
+    return batch_solve(bt, d_y, d_w, d_f, active, out_iters, out_rel, out_status);
 }
 
 extern "C" tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable) {

@@ -6,10 +6,10 @@ large over the same field, the same views, bins and measured data -- to a
 looser relative-update tolerance, for at most coarse_max iterations (a coarse
 solve that settles into the period-2 cycle of the outer iteration stops
 there); the bilinear upsampling of that solution is the start of the solve
-at full resolution. As with the learned start, a slice
-still above the tolerance after `restart_after` full-resolution iterations
-restarts from the FBP of all phases. All arithmetic runs in the library's
-kernels; this module orchestrates.
+at full resolution. As with the learned start, a slice that stalls at full
+resolution (warmstart.StartedSolver's check) or is still above the tolerance
+after `restart_after` iterations restarts from the FBP of all phases. All
+arithmetic runs in the library's kernels; this module orchestrates.
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ import torch
 
 from . import _native as nat
 from ._native import check_cnn
-from .recon import Batch, Recon, _norm_device
+from .recon import Batch, _norm_device
 
 
 def upsample(images, factor=2, out=None):
@@ -45,40 +45,32 @@ def coarse_geometry(geom):
 
 class MultigridSolver:
     """Coarse-to-fine solve of a fixed set of slice geometries to a
-    relative-update tolerance (contexts built once, at construction).
+    relative-update tolerance (contexts built once, at construction): the
+    coarse level batched, then StartedSolver at full resolution from the
+    upsampled coarse images (batched, stall check, cold restart).
     solve() returns (images, full-resolution iterations, coarse iterations,
     statuses); the full-resolution count includes a cold restart's."""
 
     def __init__(self, geoms, *, patch, window, h, mu_hat, tol, max_outer, coarse_tol=1e-3, coarse_max=50,
-                 restart_after=None, device=None):
+                 restart_after=None, stall_window=10, stall_ratio=0.6, device=None):
+        from .warmstart import StartedSolver
         self.device = _norm_device(device)
         self.n = len(geoms)
         kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=self.device)
-        self.k1 = max_outer if restart_after is None else min(restart_after, max_outer)
-        self.left = max_outer - self.k1
         self.coarse = Batch([coarse_geometry(g) for g in geoms], init="fbp", max_outer=coarse_max, tol=coarse_tol,
                             **kw)
-        self.fine = Batch(geoms, init="user", max_outer=self.k1, tol=tol, **kw)
-        self.recons = [Recon.from_geometry(g, max_outer=max(self.left, 1), tol=tol, **kw) for g in geoms]
+        self.fine = StartedSolver(geoms, tol=tol, max_outer=max_outer, restart_after=restart_after,
+                                  stall_window=stall_window, stall_ratio=stall_ratio, **kw)
 
     def solve(self, ys, ws):
         fc, itc, _, _, _ = self.coarse.solve(ys, ws)
         f0 = [upsample(f) for f in fc]
-        fs, it, _, st, _ = self.fine.solve(ys, ws, f0)
-        iters, st = list(it), list(st)
-        if self.left > 0:
-            for j in range(self.n):
-                if st[j] != 0:
-                    fj, kj, _, sj = self.recons[j].solve(ys[j], ws[j])
-                    fs[j], st[j] = fj, sj
-                    iters[j] += kj
+        fs, iters, st = self.fine.solve(ys, ws, f0)
         return fs, iters, list(itc), st
 
     def close(self):
         self.coarse.close()
         self.fine.close()
-        for rc in self.recons:
-            rc.close()
 
 
 __all__ = ["upsample", "coarse_geometry", "MultigridSolver"]

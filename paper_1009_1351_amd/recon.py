@@ -206,8 +206,10 @@ class Batch:
     def new_images(self):
         return [torch.zeros((g.n_phases, g.L, g.L), dtype=torch.float32, device=self.device) for g in self.geoms]
 
-    def solve(self, ys, ws, fs=None):
-        """Returns (fs, iterations[n], last relative updates[n], statuses[n], worst status)."""
+    def solve(self, ys, ws, fs=None, active=None):
+        """Returns (fs, iterations[n], last relative updates[n], statuses[n], worst status).
+        active (optional, n booleans): only those slices take part; the others'
+        images are left as they are and report 0 iterations."""
         n = len(self.geoms)
         fs = self.new_images() if fs is None else fs
         for g, y, w, f in zip(self.geoms, ys, ws, fs):
@@ -223,7 +225,13 @@ class Batch:
         iters = (C.c_int32 * n)()
         rel = (C.c_float * n)()
         sts = (C.c_int * n)()
-        st = nat.lib.tnlm_batch_solve(self._b, yp, wp, fp, iters, rel, sts)
+        if active is None:
+            st = nat.lib.tnlm_batch_solve(self._b, yp, wp, fp, iters, rel, sts)
+        else:
+            if len(active) != n:
+                raise ValueError("active needs one entry per slice")
+            act = (C.c_int32 * n)(*[1 if a else 0 for a in active])
+            st = nat.lib.tnlm_batch_solve_active(self._b, yp, wp, fp, act, iters, rel, sts)
         if st < 0 and all(x >= 0 for x in sts):
             check(st)
         return fs, list(iters), list(rel), list(sts), st

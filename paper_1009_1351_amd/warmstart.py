@@ -195,45 +195,97 @@ def warm_starts(recons, ys, ws, net, batch=4):
     return f_out, used
 
 
-class LearnedSolver:
-    """Learned + batched solve of a fixed set of slice geometries to a
-    relative-update tolerance (contexts are built once, at construction).
+class StartedSolver:
+    """Solve of a fixed set of slices to a relative-update tolerance from given
+    starting images, batched, with a cold restart (from the FBP of all phases,
+    on the slice's own context) of slices that do not converge from them:
 
-    solve(): warm starts (warm_starts) for all slices, then one batched solve
-    of at most `restart_after` further iterations. A slice still above the
-    tolerance then (the TNLM outer iteration can settle into a period-2 cycle
-    instead of converging) restarts cold, from the FBP of all phases, with
-    the remaining iteration budget, on its own context. Iterations are
-    counted per slice from the first one."""
+    * stall check (stall_window = m, stall_ratio = q): after 2m batched
+      iterations, a slice above the tolerance whose relative update did not
+      fall below q times its value m iterations earlier restarts at once (the
+      outer iteration has settled into its period-2 cycle; converging slices
+      contract by about 0.5 per 10 iterations); stall_window=None turns the
+      check off;
+    * a slice still above the tolerance after restart_after batched
+      iterations restarts then.
 
-    def __init__(self, geoms, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
+    A restart gets max_outer - 2m cold iterations (a late restart can so take
+    a slice past max_outer; the iterations are reported as taken). Contexts
+    are built once, at construction. solve() returns (images, iterations
+    counted from the start images, statuses)."""
+
+    def __init__(self, geoms, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, stall_window=10,
+                 stall_ratio=0.6, device=None):
         from .recon import Batch, Recon
-        self.net, self.n = net, len(geoms)
-        self.k1 = max_outer - WARM_START_ITERS
-        if restart_after is not None:
-            self.k1 = min(restart_after, self.k1)
-        self.left = max_outer - WARM_START_ITERS - self.k1
+        self.n = len(geoms)
         kw = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, device=device)
-        self.recons = [Recon.from_geometry(g, max_outer=max(self.left, 1), tol=tol, **kw) for g in geoms]
-        self.batch = Batch(geoms, init="user", max_outer=self.k1, tol=tol, **kw)
+        self.k1 = max_outer if restart_after is None else min(restart_after, max_outer)
+        self.m = stall_window if stall_window and 2 * stall_window <= self.k1 else 0
+        self.q = stall_ratio
+        self.restart = self.k1 < max_outer or self.m > 0
+        self.recons = [Recon.from_geometry(g, max_outer=max(max_outer - 2 * self.m, 1), tol=tol, **kw)
+                       for g in geoms]
+        self.seg = Batch(geoms, init="user", max_outer=self.m, tol=tol, **kw) if self.m else None
+        rest = self.k1 - 2 * self.m
+        self.rest = Batch(geoms, init="user", max_outer=rest, tol=tol, **kw) if rest > 0 else None
 
-    def solve(self, ys, ws):
-        fs, used = warm_starts(self.recons, ys, ws, self.net)
-        fs, it, _, st, _ = self.batch.solve(ys, ws, fs)
-        iters = [WARM_START_ITERS + k for k in it]
-        st = list(st)
-        if self.left > 0:
-            for j in range(self.n):
-                if st[j] != 0:
-                    fj, kj, _, sj = self.recons[j].solve(ys[j], ws[j])
-                    fs[j], st[j] = fj, sj
+    def solve(self, ys, ws, fs):
+        n = self.n
+        iters, done, cont = [0] * n, [False] * n, [True] * n
+        if self.seg is not None:
+            fs, it1, r1, st1, _ = self.seg.solve(ys, ws, fs)
+            act = [s_ != 0 for s_ in st1]
+            fs, it2, r2, st2, _ = self.seg.solve(ys, ws, fs, active=act)
+            for j in range(n):
+                iters[j] = it1[j] + (it2[j] if act[j] else 0)
+                done[j] = st1[j] == 0 or (act[j] and st2[j] == 0)
+                stalled = act[j] and not done[j] and not (r2[j] < self.q * r1[j])
+                cont[j] = not done[j] and not stalled
+        if self.rest is not None and any(cont):
+            fs, it3, _, st3, _ = self.rest.solve(ys, ws, fs, active=cont)
+            for j in range(n):
+                if cont[j]:
+                    iters[j] += it3[j]
+                    done[j] = st3[j] == 0
+        st = [0 if d else 1 for d in done]
+        if self.restart:
+            for j in range(n):
+                if not done[j]:
+                    fs[j], kj, _, st[j] = self.recons[j].solve(ys[j], ws[j])
                     iters[j] += kj
-        return fs, iters, st, used
+        return fs, iters, st
 
     def close(self):
-        self.batch.close()
+        for b in (self.seg, self.rest):
+            if b is not None:
+                b.close()
         for rc in self.recons:
             rc.close()
+
+
+class LearnedSolver:
+    """Learned + batched solve of a fixed set of slice geometries to a
+    relative-update tolerance (contexts are built once, at construction):
+    warm starts (warm_starts) for all slices, then StartedSolver from them
+    (batched iterations, stall check, cold restart of the slices that do not
+    converge from the warm start: the TNLM outer iteration can settle into a
+    period-2 cycle instead of converging). Iterations are counted per slice
+    from the first one."""
+
+    def __init__(self, geoms, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, stall_window=10,
+                 stall_ratio=0.6, device=None):
+        self.net, self.n = net, len(geoms)
+        self.inner = StartedSolver(geoms, patch=patch, window=window, h=h, mu_hat=mu_hat, tol=tol,
+                                   max_outer=max_outer - WARM_START_ITERS, restart_after=restart_after,
+                                   stall_window=stall_window, stall_ratio=stall_ratio, device=device)
+
+    def solve(self, ys, ws):
+        fs, used = warm_starts(self.inner.recons, ys, ws, self.net)
+        fs, it, st = self.inner.solve(ys, ws, fs)
+        return fs, [WARM_START_ITERS + k for k in it], st, used
+
+    def close(self):
+        self.inner.close()
 
 
 def solve_learned(geoms, ys, ws, net, *, patch, window, h, mu_hat, tol, max_outer, restart_after=None, device=None):
@@ -296,5 +348,5 @@ def train(net, X, T, *, epochs=4, batch=8, lr=1e-3, lr_final=1e-4, seed=0, log=N
     return hist
 
 
-__all__ = ["WarmStartNet", "warm_starts", "LearnedSolver", "solve_learned", "make_pairs", "train", "data_cost", "rel_change",
+__all__ = ["WarmStartNet", "warm_starts", "StartedSolver", "LearnedSolver", "solve_learned", "make_pairs", "train", "data_cost", "rel_change",
            "WARM_START_ITERS"]

@@ -208,3 +208,24 @@ def test_tile_heights_agree_bitwise(monkeypatch, N, L, d, W, same):
         outs.append(rc.regularize(gd, gd if same else vd, gd, clamp=False))
     assert torch.equal(outs[0], outs[1])
 
+
+def test_active_mask_solves_a_subset():
+    """tnlm_batch_solve_active: the active slices get exactly what a solve of
+    the whole batch gives them, the others are left untouched."""
+    cases = [synth.make_case("C1", slice_index=k, K=4) for k in range(3)]
+    c0 = cases[0]
+    kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat)
+    ys = [to_dev(c.y) for c in cases]
+    ws = [to_dev(c.w) for c in cases]
+    f0 = [recon_for(c.geom, **kw).fbp(y) for c, y in zip(cases, ys)]
+    from paper_1009_1351_amd import Batch
+    bt = Batch([c.geom for c in cases], init="user", max_outer=4, tol=0.0, **kw)
+    full, it_full, _, _, _ = bt.solve(ys, ws, [f.clone() for f in f0])
+    part, it_part, _, st_part, _ = bt.solve(ys, ws, [f.clone() for f in f0], active=[True, False, True])
+    assert torch.equal(part[0], full[0]) and torch.equal(part[2], full[2])
+    assert torch.equal(part[1], f0[1])
+    assert it_part == [4, 0, 4] and it_full == [4, 4, 4] and st_part[1] == 0
+    # resuming the middle slice alone continues from its image
+    rest, it_rest, _, _, _ = bt.solve(ys, ws, part, active=[False, True, False])
+    assert it_rest == [0, 4, 0] and torch.equal(rest[1], full[1])
+
