@@ -68,6 +68,8 @@ def test_entry_points_reject_null_context():
     assert nat.lib.tnlm_step(None, None, None, None) == -1
     assert nat.lib.tnlm_project(None, None, None) == -1
     assert nat.lib.tnlm_status_string(-5) == b"non-finite value"
+    assert nat.lib.tnlm_cost(None, None, None, None, None, None, None) == -1
+    assert nat.lib.tnlm_batch_solve_active(None, None, None, None, None, None, None, None) == -1
 
 
 def test_nonfinite_view_angle_rejected():
