@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import announce, recon_for, to_dev, to_host
+from gpu_common import announce, f32, recon_for, rel_l2_per_phase, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -114,7 +114,7 @@ def test_corrupted_checkpoint_is_rejected(tmp_path):
         nt.load(tmp_path / "short.ckpt")
 
 
-def test_warm_start_pipeline_small():
+def test_warm_start_pipeline_small(orc):
     from paper_1009_1351_amd.warmstart import WarmStartNet, make_pairs, train, warm_starts
     cases = [synth.make_case("C5train", slice_index=s, L=48, V=24, B=64, patch=5, window=9) for s in range(6)]
     X, T, its, rels = make_pairs(cases, device=torch.device("cuda"), chunk=6, tol=1e-3, max_outer=60, patch=5, window=9)
@@ -128,6 +128,7 @@ def test_warm_start_pipeline_small():
     ws = [to_dev(c.w) for c in cases[:2]]
     f1s, used = warm_starts(recons, ys, ws, nt)
     assert all(torch.isfinite(f).all() for f in f1s)
+    f_first = k_first = None
     for rc, y, w, f1, u in zip(recons, ys, ws, f1s, used):
         # the returned image is WARM_START_ITERS outer iterations from the chosen start
         cold = cold_start(rc, y, w)
@@ -135,6 +136,20 @@ def test_warm_start_pipeline_small():
             assert torch.equal(f1, cold)
         f, k, r, st = rc.solve(y, w, f1.clone())
         assert st == 0 and r < 1e-3
+        if f_first is None:
+            f_first, k_first = f, k
+    # the oracle judges the final image of the learned path: its own solve of
+    # the first slice from the cold start to the same tolerance. Both stop at
+    # a relative update below 1e-3 of a contraction (about 0.9 per iteration
+    # at this size), so each is within ~1e-2 of the fixed point.
+    c = cases[0]
+    G = orc.Geometry(c.geom)
+    prm = orc.case_params(c, patch=5, window=9, h=float(np.float32(c.h)), mu_hat=float(np.float32(c.mu_hat)),
+                          tol=1e-3, max_outer=60)
+    ref, kr, relr, _ = orc.solve(G, prm, f32(c.y), f32(c.w))
+    d = rel_l2_per_phase(to_host(f_first), ref).max()
+    announce(f"learned path vs oracle solve: {k_first} vs {kr} iterations, max rel L2 per phase {d:.2e}")
+    assert relr < 1e-3 and d < 2e-2
 
 
 def cold_start(rc, y, w):
