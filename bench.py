@@ -44,14 +44,15 @@ def log(msg):
 
 def crossings(geom) -> float:
     """Number of nonzeros of P (ray-pixel crossings) over all phases, from the
-    chord of each ray through the image square: |dc| + |dr| + 1 cells per ray."""
+    chord of each ray through the image square: chord (|ux| + |uy|) / D cells
+    per ray in expectation (a chord starts and ends on grid lines)."""
     src, u = geom.rays()
     S = geom.fov_mm
     with np.errstate(divide="ignore", invalid="ignore"):
         tx = np.stack([(-S / 2 - src[..., 0]) / u[..., 0], (S / 2 - src[..., 0]) / u[..., 0]])
         ty = np.stack([(-S / 2 - src[..., 1]) / u[..., 1], (S / 2 - src[..., 1]) / u[..., 1]])
     chord = np.maximum(np.minimum(tx.max(0), ty.max(0)) - np.maximum(tx.min(0), ty.min(0)), 0.0)
-    n = np.where(chord > 0, chord * (np.abs(u[..., 0]) + np.abs(u[..., 1])) / geom.pixel_mm + 1.0, 0.0)
+    n = np.where(chord > 0, chord * (np.abs(u[..., 0]) + np.abs(u[..., 1])) / geom.pixel_mm, 0.0)
     return float(n.sum())
 
 
