@@ -670,9 +670,11 @@ static tnlm_status engine_solve(Engine *E, const float *y, const float *w, float
             for (int s = 0; s < ns; ++s) done += hf[s] != 0;
             if (done == ns) break;
             // finished slices keep their skip flags; once a quarter of the
-            // batch (or more) has finished since the last cut, re-cut the work
-            // tables so the remaining slices spread over all XCDs again
-            if (ns > 1 && 4 * (done - ndone) >= ns) {
+            // slices that were running at the last cut has finished, re-cut
+            // the work tables so the remaining ones spread over all XCDs again
+            // (measured against the whole batch, the last few slices of a
+            // batch ran on the few XCDs whose ranges still held them)
+            if (ns > 1 && done > ndone && 4 * (done - ndone) >= ns - ndone) {
                 std::vector<char> active(ns);
                 for (int s = 0; s < ns; ++s) active[s] = hf[s] == 0;
                 if ((rs = restage(E, active)) != TNLM_OK) break;

@@ -125,6 +125,7 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--train-time", type=float, default=420.0)
     ap.add_argument("--eval-slices", type=int, default=32)
+    ap.add_argument("--eval-offset", type=int, default=10_000, help="first slice seed of the evaluation set")
     ap.add_argument("--eval-L", type=int, default=512)
     ap.add_argument("--eval-B", type=int, default=720)
     ap.add_argument("--eval-max-outer", type=int, default=600)
@@ -175,7 +176,8 @@ def main():
         del X, T
         torch.cuda.empty_cache()
     if a.eval_slices > 0:
-        ev = [synth.make_case("C5eval", slice_index=10_000 + k, L=a.eval_L, B=a.eval_B) for k in range(a.eval_slices)]
+        ev = [synth.make_case("C5eval", slice_index=a.eval_offset + k, L=a.eval_L, B=a.eval_B)
+              for k in range(a.eval_slices)]
         log("evaluation ...")
         report["eval"] = eval_warm_vs_cold(net, ev, dev, max_outer=a.eval_max_outer, restart_after=a.restart_after,
                                            coarse_max=a.coarse_max)
