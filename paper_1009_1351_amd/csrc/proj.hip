@@ -11,8 +11,9 @@
 // enter the same min/max, so the two kernels use bitwise-identical matrix
 // entries and <P f, q> = <f, P^T q> holds up to summation order.
 //
-// Forward: one lane per ray, lanes = consecutive bins of one view (adjacent
-// rays walk neighbouring pixels, writes are coalesced). Transpose: one lane
+// Forward: one lane per ray, lanes = consecutive bins of one view, walking
+// the image row by row in step (adjacent rays read neighbouring pixels of one
+// row, writes are coalesced). Transpose: one lane
 // per pixel, a deterministic gather over views and the pixel's candidate
 // bins (no floating-point atomics). Both are persistent over the batch's
 // ragged slice table.
@@ -39,69 +40,126 @@ __device__ __forceinline__ float image_at(__amdgpu_buffer_rsrc_t img, int byte_o
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, byte_off, 0, 0));
 }
 
-// One ray: Siddon walk of one phase image (L x L) along plane table A and
-// ray point/direction O.
-__device__ __forceinline__ float walk_ray(const float4 A, const float4 O, __amdgpu_buffer_rsrc_t img, int L,
-                                          float X0, float invD) {
-    const float tx0 = plane_t(0, A.x, A.y), txL = plane_t(L, A.x, A.y);
-    const float ty0 = plane_t(0, A.z, A.w), tyL = plane_t(L, A.z, A.w);
-    const float tin = fmaxf(fminf(tx0, txL), fminf(ty0, tyL));
-    const float tout = fminf(fmaxf(tx0, txL), fmaxf(ty0, tyL));
-    if (!(tout > tin)) return 0.0f;
-    const int dc = A.x > 0.0f ? 1 : -1, dr = A.z > 0.0f ? 1 : -1;
-    const int hc = dc > 0 ? 1 : 0, hr = dr > 0 ? 1 : 0;   // hi plane of cell c = c + hc
-    // first cell: estimate from the entry point, then settle it on the plane
-    // values themselves (lo plane <= tin < hi plane)
-    int c = (int)floorf((fmaf(tin, O.z, O.x) - X0) * invD);
-    int r = (int)floorf((fmaf(tin, O.w, O.y) - X0) * invD);
-    c = min(max(c, 0), L - 1);
-    r = min(max(r, 0), L - 1);
-    for (int it = 0; it < 4; ++it) {
-        if (plane_t(c + 1 - hc, A.x, A.y) > tin && (unsigned)(c - dc) < (unsigned)L) c -= dc;
-        else if (plane_t(c + hc, A.x, A.y) <= tin && (unsigned)(c + dc) < (unsigned)L) c += dc;
-        if (plane_t(r + 1 - hr, A.z, A.w) > tin && (unsigned)(r - dr) < (unsigned)L) r -= dr;
-        else if (plane_t(r + hr, A.z, A.w) <= tin && (unsigned)(r + dr) < (unsigned)L) r += dr;
+__device__ __forceinline__ float cell_clip(float xl, float xh, float yl, float yh) {
+    return fmaxf(fminf(xh, yh) - fmaxf(xl, yl), 0.0f);
+}
+
+// Offset that the image's buffer resource turns into a read of 0 without a
+// memory access (beyond the L x L image for every L the engine accepts).
+constexpr int kNoCell = 0x40000000;
+
+// Row-synchronous walk of one wave's rays over one phase image (L x L). The
+// plane tables A (x planes in .x/.y, y planes in .z/.w) and ray points O come
+// in the wave's frame, in which every ray of the wave crosses about one
+// column per row or fewer. Pass p visits image row p counted along the rays'
+// row direction for all lanes at once, so the lanes of a wave read
+// neighbouring cells of one row (two per lane: the current column and the
+// next) rather than drifting apart by their different numbers of column
+// crossings. The length of each cell is the clip of the transpose kernel and
+// cells are added in the order the ray meets them (a ray that reaches the next
+// column exactly at the row's upper plane enters it with length 0 first), so
+// the sum is bitwise that of a walk crossing one grid line at a time. The loop
+// ends after the last row, or once every lane's ray has left the image through
+// a side; a ray crossing two columns in one row takes the rare inner loop.
+// Must be called by all lanes of the wave; lanes with valid = false add nothing.
+__device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool valid,
+                                           __amdgpu_buffer_rsrc_t img, int L, float X0, float invD) {
+    int pin = L, c = 0, dc = 1, dr = 1, hc = 1, hr = 1;
+    float tin = 0.0f;
+    bool hit = false;
+    if (valid) {
+        const float tx0 = plane_t(0, A.x, A.y), txL = plane_t(L, A.x, A.y);
+        const float ty0 = plane_t(0, A.z, A.w), tyL = plane_t(L, A.z, A.w);
+        tin = fmaxf(fminf(tx0, txL), fminf(ty0, tyL));
+        const float tout = fminf(fmaxf(tx0, txL), fmaxf(ty0, tyL));
+        if (tout > tin) {
+            hit = true;
+            dc = A.x > 0.0f ? 1 : -1;
+            dr = A.z > 0.0f ? 1 : -1;
+            hc = dc > 0 ? 1 : 0;   // hi plane of cell c = c + hc
+            hr = dr > 0 ? 1 : 0;
+            // entry cell: estimate from the entry point, then settle it on the
+            // plane values themselves (lo plane <= tin < hi plane)
+            c = (int)floorf((fmaf(tin, O.z, O.x) - X0) * invD);
+            int r = (int)floorf((fmaf(tin, O.w, O.y) - X0) * invD);
+            c = min(max(c, 0), L - 1);
+            r = min(max(r, 0), L - 1);
+            for (int it = 0; it < 4; ++it) {
+                if (plane_t(c + 1 - hc, A.x, A.y) > tin && (unsigned)(c - dc) < (unsigned)L) c -= dc;
+                else if (plane_t(c + hc, A.x, A.y) <= tin && (unsigned)(c + dc) < (unsigned)L) c += dc;
+                if (plane_t(r + 1 - hr, A.z, A.w) > tin && (unsigned)(r - dr) < (unsigned)L) r -= dr;
+                else if (plane_t(r + hr, A.z, A.w) <= tin && (unsigned)(r + dr) < (unsigned)L) r += dr;
+            }
+            pin = dr > 0 ? r : L - 1 - r;   // pass of the entry row
+        }
     }
-    // Walk: tcur is the lo plane of the current cell (max of its x/y lo
-    // planes); the next crossing is min(txh, tyh). Each segment equals the
-    // clip of the cell computed by the transpose kernel, bit for bit. One
-    // grid line is crossed per pass, x first on a tie (the cell entered then
-    // has a zero-length segment, as its clip has). T is monotone in k and the
-    // exit planes' values bound tout, so tn reaches tout after at most L + 1
-    // x-steps and L + 1 y-steps: the loop ends within 2L + 3 passes.
-    float fkx = (float)(c + hc), fky = (float)(r + hr);
-    float txh = plane_t(c + hc, A.x, A.y), tyh = plane_t(r + hr, A.z, A.w);
-    float tcur = fmaxf(plane_t(c + 1 - hc, A.x, A.y), plane_t(r + 1 - hr, A.z, A.w));
+    int p0 = pin;   // first pass of the wave
+    for (int m = 32; m > 0; m >>= 1) p0 = min(p0, __shfl_xor(p0, m, 64));
+    p0 = wave_uniform(p0);
+    const int r0 = dr > 0 ? p0 : L - 1 - p0;
     const float dcf = (float)dc, drf = (float)dr;
     const int ox = 4 * dc, oy = 4 * dr * L;
-    int off = 4 * (r * L + c);
-    float val = image_at(img, off);
+    float fkx = (float)(c + hc), fky = (float)(r0 + hr);
+    float txh = plane_t(c + hc, A.x, A.y);
+    float tyl = plane_t(r0 + 1 - hr, A.z, A.w);
+    int rowoff = 4 * r0 * L;
+    bool dead = !hit;
+    bool live = hit && p0 >= pin;
+    int o1 = live ? rowoff + 4 * c : kNoCell;
+    float v1 = image_at(img, o1), v2 = image_at(img, o1 + ox);
     float acc = 0.0f;
-    for (;;) {
-        const bool sx = txh <= tyh;
-        const float tn = fminf(fminf(txh, tyh), tout);
-        off += sx ? ox : oy;
-        fkx += sx ? dcf : 0.0f;
-        fky += sx ? 0.0f : drf;
-        const float nval = image_at(img, off);   // next cell, in flight during this one
-        acc = fmaf(tn - tcur, val, acc);
-        if (!(tn < tout)) break;   // the cell just added was the last one
-        tcur = tn;
-        val = nval;
-        txh = fmaf(fkx, A.x, A.y);
-        tyh = fmaf(fky, A.z, A.w);
+    for (int p = p0; p < L; ++p) {
+        // At the start of a row a live lane's column c holds its ray and the
+        // column's upper x plane lies beyond the row's lower y plane
+        // (txh > tyl), so the clip of (r, c) is non-negative and that of
+        // (r, c + dc) has max(txh, tyl) = txh: both are the transpose
+        // kernel's clips without its clamp. The lower x plane of column c
+        // is at most tyl in every row but the entry row, where it is tin or
+        // at most tin = tyl, so max(x_lo, tyl) = max(tin, tyl) throughout.
+        // Lanes that are not live read 0.
+        const float tyh = fmaf(fky, A.z, A.w);
+        const float txn = fmaf(fkx + dcf, A.x, A.y);
+        const float l1 = fminf(txh, tyh) - fmaxf(tin, tyl);
+        const float l2 = fminf(txn, tyh) - txh;
+        const bool cross = live && txh <= tyh;   // reaches the next column in this row
+        const bool in2 = (unsigned)(c + dc) < (unsigned)L;
+        const bool take2 = cross && in2;
+        acc = fmaf(l1, v1, acc);
+        acc = fmaf(take2 ? l2 : 0.0f, v2, acc);
+        dead = dead || (cross && !in2);   // left the image through a side
+        c = take2 ? c + dc : c;
+        fkx = take2 ? fkx + dcf : fkx;
+        txh = take2 ? txn : txh;
+        while (take2 && txh <= tyh) {   // a further column in the same row
+            if ((unsigned)(c + dc) >= (unsigned)L) {
+                dead = true;
+                break;
+            }
+            const float tx3 = fmaf(fkx + dcf, A.x, A.y);
+            acc = fmaf(cell_clip(txh, tx3, tyl, tyh), image_at(img, rowoff + 4 * (c + dc)), acc);
+            c += dc;
+            fkx += dcf;
+            txh = tx3;
+        }
+        tyl = tyh;
+        fky += drf;
+        rowoff += oy;
+        if (__ballot(!dead) == 0) break;
+        live = !dead && p + 1 >= pin;
+        o1 = live ? rowoff + 4 * c : kNoCell;
+        v1 = image_at(img, o1);   // next row's cells, in flight during the checks above
+        v2 = image_at(img, o1 + ox);
     }
     return acc;
 }
 
-// Image stacks are row-major, (r, c) at r L + c. Lanes of a projector wave
-// are neighbouring rays: for a view whose rays run mostly along y they sit in
-// one row at neighbouring columns (few cache lines per load), for a view
-// whose rays run mostly along x they sit in neighbouring rows (one line per
-// lane). The latter views walk a transposed copy, (r, c) at c L + r, with
-// the roles of the axes exchanged; the walk computes the same segments (a
-// tie now steps the other axis first, through a cell of zero length), so the
-// sum is bitwise the same for a finite image.
+// Image stacks are row-major, (r, c) at r L + c. A projector wave walks rows
+// in step, which suits rays that run mostly along y: its lanes then sit in
+// one row at neighbouring columns (few cache lines per load). A wave whose
+// rays run mostly along x walks a transposed copy, (r, c) at c L + r, with
+// the roles of the axes exchanged; the cells and their lengths are the same
+// (at a grid corner the zero-length cell passed through is the other one), so
+// the sum is bitwise the same for a finite image.
 constexpr int kTr = 32;
 
 int tr_blocks(const SliceDesc &s) {
@@ -164,18 +222,22 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
         const int b = bx * kRaysPerBlock + threadIdx.x;
         const long long ray = ((long long)i * sd.V + v) * sd.B + b;   // within the slice
         const int L = sd.L;
-        const float4 vs = load_const(bt.vt, sd.view0 + (long long)i * sd.V + v);   // cos th, sin th in z, w
-        const bool tr = fabsf(vs.z) > fabsf(vs.w);   // central ray mostly along x
-        const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.img0 + (long long)i * L * L, L);
-        float acc = 0.0f;
-        if (b < sd.B) {
-            float4 A = bt.rt0[sd.ray0 + ray], O = bt.rt1[sd.ray0 + ray];
-            if (tr) {
-                A = make_float4(A.z, A.w, A.x, A.y);
-                O = make_float4(O.y, O.x, O.w, O.z);
-            }
-            acc = walk_ray(A, O, img, L, sd.X0, 1.0f / sd.D);
+        const bool valid = b < sd.B;
+        float4 A = make_float4(1.0f, 0.0f, 1.0f, 0.0f), O = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+        if (valid) {
+            A = bt.rt0[sd.ray0 + ray];
+            O = bt.rt1[sd.ray0 + ray];
         }
+        // the wave walks the transposed image, axes exchanged, when most of
+        // its rays cross columns faster than rows
+        const bool xmaj = valid && fabsf(A.x) < fabsf(A.z);
+        const bool tr = wave_uniform(2 * __popcll(__ballot(xmaj)) > __popcll(__ballot(valid)));
+        if (tr) {
+            A = make_float4(A.z, A.w, A.x, A.y);
+            O = make_float4(O.y, O.x, O.w, O.z);
+        }
+        const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.img0 + (long long)i * L * L, L);
+        const float acc = walk_rows(A, O, valid, img, L, sd.X0, 1.0f / sd.D);
         double part = 0.0;
         if (b < sd.B) {
             const long long e = sd.sino0 + ray;
