@@ -95,6 +95,35 @@ def test_tiny_geometries_match_oracle(orc, shape):
     assert rel_l2_per_phase(to_host(out), oref).max() < 1e-4
 
 
+# Few bins make one wave span the whole fan (up to 72 degrees from its
+# frame's axis, several columns per row); 70 bins leave a partial second wave.
+ENTRY_SHAPES = [(1, 10, 6, 20, 0.0), (1, 9, 5, 70, 0.3), (2, 7, 3, 33, 0.785398)]
+
+
+@pytest.mark.parametrize("shape", ENTRY_SHAPES)
+def test_projector_entries_match_bitwise(shape):
+    """P and P^T use the same FP32 matrix entries, bit for bit: projecting the
+    unit image of pixel j yields column j of P exactly (every other cell of a
+    ray adds an exact zero), back-projecting the unit sinogram of ray i yields
+    row i of P^T exactly, and the two matrices must be identical."""
+    N, L, V, B, th0 = shape
+    announce(f"projector entries N={N} L={L} V={V} B={B} theta0={th0}")
+    geom = synth.ScanGeometry(n_phases=N, L=L, n_views=V, n_bins=B, theta0=th0)
+    rc = recon_for(geom, patch=3, window=3)
+    P = np.zeros((N, V * B, L * L), np.float32)
+    for j in range(L * L):
+        e = np.zeros((N, L, L), np.float32)
+        e[:, j // L, j % L] = 1.0
+        P[:, :, j] = to_host(rc.project(to_dev(e))).reshape(N, V * B)
+    Pt = np.zeros_like(P)
+    for i in range(V * B):
+        e = np.zeros((N, V, B), np.float32)
+        e[:, i // B, i % B] = 1.0
+        Pt[:, i, :] = to_host(rc.backproject(to_dev(e))).reshape(N, L * L)
+    assert (P > 0).sum() > L * V * N   # the rays cross the image
+    np.testing.assert_array_equal(P.view(np.uint32), Pt.view(np.uint32))
+
+
 def test_adjoint_on_gpu():
     geom = small_geom(3, 56, 48, 80)
     rng = np.random.default_rng(103)
