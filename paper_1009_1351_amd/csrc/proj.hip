@@ -58,13 +58,14 @@ constexpr int kNoCell = 0x40000000;
 // crossings. The length of each cell is the clip of the transpose kernel and
 // cells are added in the order the ray meets them (a ray that reaches the next
 // column exactly at the row's upper plane enters it with length 0 first), so
-// the sum is bitwise that of a walk crossing one grid line at a time. The loop
-// ends after the last row, or once every lane's ray has left the image through
-// a side; a ray crossing two columns in one row takes the rare inner loop.
+// the sum is bitwise that of a walk crossing one grid line at a time. The wave
+// runs from the first entry row to the last exit row of its rays; a lane that
+// leaves through a side stops adding there, and a ray crossing two columns in
+// one row takes the rare inner loop.
 // Must be called by all lanes of the wave; lanes with valid = false add nothing.
 __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool valid,
                                            __amdgpu_buffer_rsrc_t img, int L, float X0, float invD) {
-    int pin = L, c = 0, dc = 1, dr = 1, hc = 1, hr = 1;
+    int pin = L, pout = -1, c = 0, dc = 1, dr = 1, hc = 1, hr = 1;
     float tin = 0.0f;
     bool hit = false;
     if (valid) {
@@ -91,11 +92,20 @@ __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool 
                 else if (plane_t(r + hr, A.z, A.w) <= tin && (unsigned)(r + dr) < (unsigned)L) r += dr;
             }
             pin = dr > 0 ? r : L - 1 - r;   // pass of the entry row
+            // pass of the exit row, from the exit point, with two rows of
+            // margin for its rounding (rows past the exit add nothing)
+            int re = (int)floorf((fmaf(tout, O.w, O.y) - X0) * invD);
+            re = min(max(re, 0), L - 1);
+            pout = min((dr > 0 ? re : L - 1 - re) + 2, L - 1);
         }
     }
-    int p0 = pin;   // first pass of the wave
-    for (int m = 32; m > 0; m >>= 1) p0 = min(p0, __shfl_xor(p0, m, 64));
+    int p0 = pin, p1 = pout;   // first and last pass of the wave
+    for (int m = 32; m > 0; m >>= 1) {
+        p0 = min(p0, __shfl_xor(p0, m, 64));
+        p1 = max(p1, __shfl_xor(p1, m, 64));
+    }
     p0 = wave_uniform(p0);
+    p1 = wave_uniform(p1);
     const int r0 = dr > 0 ? p0 : L - 1 - p0;
     const float dcf = (float)dc, drf = (float)dr;
     const int ox = 4 * dc, oy = 4 * dr * L;
@@ -108,7 +118,7 @@ __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool 
     int o1 = live ? rowoff + 4 * c : kNoCell;
     float v1 = image_at(img, o1), v2 = image_at(img, o1 + ox);
     float acc = 0.0f;
-    for (int p = p0; p < L; ++p) {
+    for (int p = p0; p <= p1; ++p) {
         // At the start of a row a live lane's column c holds its ray and the
         // column's upper x plane lies beyond the row's lower y plane
         // (txh > tyl), so the clip of (r, c) is non-negative and that of
@@ -144,7 +154,6 @@ __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool 
         tyl = tyh;
         fky += drf;
         rowoff += oy;
-        if (__ballot(!dead) == 0) break;
         live = !dead && p + 1 >= pin;
         o1 = live ? rowoff + 4 * c : kNoCell;
         v1 = image_at(img, o1);   // next row's cells, in flight during the checks above
