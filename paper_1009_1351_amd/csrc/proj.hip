@@ -156,7 +156,7 @@ __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool 
         rowoff += oy;
         live = !dead && p + 1 >= pin;
         o1 = live ? rowoff + 4 * c : kNoCell;
-        v1 = image_at(img, o1);   // next row's cells, in flight during the checks above
+        v1 = image_at(img, o1);   // next row's cells, in flight during the next pass's plane arithmetic
         v2 = image_at(img, o1 + ox);
     }
     return acc;
