@@ -329,22 +329,30 @@ __device__ __forceinline__ void bp_block_ray(const float4 A, const float qb, flo
     a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
 }
 
-// Two candidates per pass, both requested before either is used. On an odd
-// count the last pass reads candidate b1 twice and adds its second copy with
-// weight 0 (a finite segment times +0 leaves every sum unchanged), so the
-// additions happen in the same order as one candidate per pass.
+// Two candidates per pass, both requested before either is used; an odd last
+// candidate takes a pass of its own, so the additions happen in the same order
+// as one candidate per pass. The view's plane records and sinogram values are
+// read through buffer resources (wave-uniform bases) at per-lane 32-bit
+// offsets: one offset step per pass instead of 64-bit address arithmetic.
+__device__ __forceinline__ float4 rsrc_f4(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+}
+
 template <bool XP, bool YP>
-__device__ __forceinline__ void bp_block_oriented(const float4 *__restrict__ Av, const float *__restrict__ qv, int b0,
+__device__ __forceinline__ void bp_block_oriented(__amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rq, int b0,
                                                   int b1, float fc0, float fr0, float &a00, float &a01, float &a10,
                                                   float &a11) {
-    for (int b = b0; b <= b1; b += 2) {
-        const int bn = min(b + 1, b1);
-        const float4 A = Av[b], An = Av[bn];
-        const float qb = qv[b], qr = qv[bn];
-        const float qn = b + 1 <= b1 ? qr : 0.0f;
+    int off = 16 * b0;          // byte offset of the candidate's plane record
+    const int last = 16 * b1;   // that of the last candidate
+    for (; off < last; off += 32) {   // at least two candidates left
+        const float4 A = rsrc_f4(ra, off), An = rsrc_f4(ra, off + 16);
+        const float qb = image_at(rq, off >> 2), qn = image_at(rq, (off >> 2) + 4);
         bp_block_ray<XP, YP>(A, qb, fc0, fr0, a00, a01, a10, a11);
         bp_block_ray<XP, YP>(An, qn, fc0, fr0, a00, a01, a10, a11);
     }
+    if (off == last) bp_block_ray<XP, YP>(rsrc_f4(ra, off), image_at(rq, off >> 2), fc0, fr0, a00, a01, a10, a11);
 }
 
 int bp_blocks(const SliceDesc &s) {
@@ -407,12 +415,16 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
                     // comparison per side (the same values as the general form)
                     const bool xpos = ((vb.z & 1) != 0) == (b0 < vb.x);
                     const bool ypos = ((vb.z & 2) != 0) == (b0 < vb.y);
+                    const __amdgpu_buffer_rsrc_t ra =
+                        __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(Av), (short)0, B * 16, 0x00020000);
+                    const __amdgpu_buffer_rsrc_t rq =
+                        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(qv), (short)0, B * 4, 0x00020000);
                     if (xpos) {
-                        if (ypos) bp_block_oriented<true, true>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
-                        else bp_block_oriented<true, false>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        if (ypos) bp_block_oriented<true, true>(ra, rq, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        else bp_block_oriented<true, false>(ra, rq, b0, b1, fc0, fr0, a00, a01, a10, a11);
                     } else {
-                        if (ypos) bp_block_oriented<false, true>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
-                        else bp_block_oriented<false, false>(Av, qv, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        if (ypos) bp_block_oriented<false, true>(ra, rq, b0, b1, fc0, fr0, a00, a01, a10, a11);
+                        else bp_block_oriented<false, false>(ra, rq, b0, b1, fc0, fr0, a00, a01, a10, a11);
                     }
                 } else {
                     for (int b = b0; b <= b1; ++b) {
