@@ -52,7 +52,6 @@ def h_from_rel(h_rel: float, patch: int) -> float:
 class Case:
     name: str
     geom: ScanGeometry
-    truth: np.ndarray   # [N][L][L] float64 (supersampled phantom)
     y: np.ndarray       # [N][V][B] float64
     w: np.ndarray       # [N][V][B] float64, inverse variance
     I0: float
@@ -66,6 +65,15 @@ class Case:
     max_outer: int
     tol: float
     ellipses: list = None   # per phase: the phantom's ellipses (for regions of interest)
+    _truth: np.ndarray = dataclasses.field(default=None, repr=False)
+
+    @property
+    def truth(self) -> np.ndarray:
+        """[N][L][L] float64 phantom (4x4 supersampled), rasterised on first use."""
+        if self._truth is None:
+            L = self.geom.L
+            self._truth = np.stack([rasterize(el, L, self.geom.fov_mm) for el in self.ellipses])
+        return self._truth
 
 
 CONFIGS = {
@@ -112,19 +120,17 @@ def make_case(config: str = "C1", slice_index: int = 0, n_phases: int = 10, *, L
     if randomize is None:
         randomize = config in ("C3", "C5train", "C5eval", "C4")
     geom = ScanGeometry(n_phases=n_phases, L=L, n_views=V, n_bins=B)
-    phases, truth = [], np.empty((n_phases, L, L))
+    phases = []
     for i in range(n_phases):
         rng = np.random.Generator(np.random.PCG64(SEED + slice_index))  # same draws for every phase
-        el = thorax_phantom(i, n_phases, geom.pixel_mm, rng=rng, randomize=randomize)
-        phases.append(el)
-        truth[i] = rasterize(el, L, geom.fov_mm)
+        phases.append(thorax_phantom(i, n_phases, geom.pixel_mm, rng=rng, randomize=randomize))
     pbar = analytic_sinogram(geom, phases)
     y = np.empty_like(pbar)
     w = np.empty_like(pbar)
     for i in range(n_phases):
         rng = np.random.Generator(np.random.PCG64(SEED + 10**6 + 1000 * slice_index + i))
         y[i], w[i] = noisy_measurement(pbar[i], I0, rng, law=law)
-    return Case(name=f"{config}/s{slice_index}", geom=geom, truth=truth, y=y, w=w, I0=I0, patch=patch,
+    return Case(name=f"{config}/s{slice_index}", geom=geom, y=y, w=w, I0=I0, patch=patch,
                 window=window, h=h_from_rel(h_rel, patch), mu_hat=mu_hat, beta=beta, m1=m1, m2=m2,
                 max_outer=K, tol=tol, ellipses=phases)
 

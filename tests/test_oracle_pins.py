@@ -483,3 +483,178 @@ def test_fixed_guide_of_constant_image_gives_window_means():
     np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-15)
     # and the weights from g itself differ (the guide is really used)
     assert np.abs(oracle.gauss_jacobi(g, d, W, 0.01, mu, m2=1) - expect).max() > 1e-6
+
+
+# ------------------------------------------- composition of one outer iteration
+def dense_weights(gi, gj, d, W, h):
+    """Eq. 8 weights as an [L*L, L*L] matrix: plain SSD of edge-clamped d x d
+    patches, the W x W window truncated to the image, softmax over it."""
+    L = gi.shape[0]
+    R = W // 2
+    Pi = patch_array(gi, d).reshape(L * L, -1)
+    Pj = patch_array(gj, d).reshape(L * L, -1)
+    rr, cc = np.divmod(np.arange(L * L), L)
+    win = (np.abs(rr[:, None] - rr[None]) <= R) & (np.abs(cc[:, None] - cc[None]) <= R)
+    D = ((Pi[:, None, :] - Pj[None, :, :]) ** 2).sum(-1)
+    D = np.where(win, D, np.inf)
+    wts = np.exp(-(D - D.min(1, keepdims=True)) / h ** 2)
+    return wts / wts.sum(1, keepdims=True)
+
+
+def krylov_cgls(A, w, y, u0, m):
+    """The m-th CGLS iterate as the minimiser of ||sqrt(w)(y - A u)|| over
+    u0 + K_m(A_n^T A_n, A_n^T r0) (dense basis, no CGLS recurrences)."""
+    An = np.sqrt(w)[:, None] * A
+    r0 = np.sqrt(w) * y - An @ u0
+    v = An.T @ r0
+    K = []
+    for _ in range(m):
+        K.append(v / np.linalg.norm(v))
+        v = An.T @ (An @ K[-1])
+    Q, _ = np.linalg.qr(np.stack(K, 1))
+    c, *_ = np.linalg.lstsq(An @ Q, r0, rcond=None)
+    return u0 + Q @ c
+
+
+def dense_outer_iteration(A, geom, y, w, f, m1, m2, d, W, h, mu):
+    """One iteration of the TNLM algorithm box from dense matrices: g = CGLS
+    (M1 steps, per phase); weights from g (Eq. 8); M2 Jacobi sweeps of Eq. 7
+    from u = g with those weights; f = max(u, 0); and the relative update."""
+    N, L, VB = geom.n_phases, geom.L, geom.n_views * geom.n_bins
+    n = L * L
+    g = np.stack([krylov_cgls(A[i * VB:(i + 1) * VB, i * n:(i + 1) * n], w[i].ravel(), y[i].ravel(),
+                              f[i].ravel(), m1) for i in range(N)])
+    Om = {(i, j): dense_weights(g[i].reshape(L, L), g[j].reshape(L, L), d, W, h)
+          for i in range(N) for j in ((i - 1) % N, (i + 1) % N)}
+    u = g.copy()
+    for _ in range(m2):
+        u = np.stack([g[i] / (1 + mu) + mu / (2 * mu + 2) * (Om[i, (i - 1) % N] @ u[(i - 1) % N] +
+                                                             Om[i, (i + 1) % N] @ u[(i + 1) % N])
+                      for i in range(N)])
+    fn = np.maximum(u, 0.0).reshape(N, L, L)
+    rel = np.linalg.norm(fn - f) / np.linalg.norm(fn)
+    return fn, rel, g.reshape(N, L, L)
+
+
+def _dense_problem(seed, N=3, L=6, V=10, B=12):
+    geom = small_geom(N=N, L=L, V=V, B=B)
+    A = dense_P_clip(geom)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 2.0, size=(N, V, B))
+    f0 = synth.configs.smooth_random_images((N, L, L), seed, passes=1)
+    # data of an image with negative pixels, so the data step leaves negative
+    # pixels and the place of the positivity clamp matters
+    z = rng.normal(-0.01, 0.02, size=f0.shape)
+    y = (A @ (f0 + z).ravel()).reshape(N, V, B) + rng.normal(0.0, 0.05, size=(N, V, B))
+    return geom, A, y, w, f0
+
+
+def test_step_is_cgls_then_jacobi_then_clamp(orc):
+    """orc_step = CGLS from f^(k-1) (M1 = 3) -> weights from its output g ->
+    M2 = 2 Jacobi sweeps starting at g -> clamp, and the relative update
+    ||f^k - f^(k-1)|| / ||f^k|| (TNLM and Gauss-Jacobi boxes), against the
+    dense composition above."""
+    geom, A, y, w, f0 = _dense_problem(21)
+    d, W, h, mu = 3, 5, 0.02, 0.8
+    G = orc.Geometry(geom)
+    prm = orc.params(patch=d, window=W, h=h, mu_hat=mu, m1=3, m2=2)
+    got, rel = orc.step(G, prm, y, w, f0)
+    exp, rel_exp, g = dense_outer_iteration(A, geom, y, w, f0, 3, 2, d, W, h, mu)
+    assert g.min() < -0.01 and (exp == 0).sum() > 5     # the clamp acts after the sweeps
+    np.testing.assert_allclose(got, exp, rtol=1e-9, atol=1e-12)
+    assert abs(rel - rel_exp) <= 1e-9 * rel_exp
+    # the alternatives that this composition excludes differ by far more
+    # than the tolerance: weights or values from f^(k-1), clamp before the sweeps
+    alt_guide = orc.gauss_jacobi(g, d, W, h, mu, m2=2, guide=f0)
+    alt_clamp = orc.gauss_jacobi(np.maximum(g, 0), d, W, h, mu, m2=2)
+    assert np.abs(alt_guide - exp).max() > 1e-4 and np.abs(alt_clamp - exp).max() > 1e-4
+
+
+def test_solve_is_fbp_then_steps(orc):
+    """orc_solve = f^(0) (FBP of all phases, or the caller's image) followed by
+    outer iterations; the history holds each iteration's relative update."""
+    geom, A, y, w, f0 = _dense_problem(22)
+    d, W, h, mu = 3, 5, 0.02, 0.8
+    G = orc.Geometry(geom)
+    prm = orc.params(patch=d, window=W, h=h, mu_hat=mu, m1=2, m2=1, max_outer=3)
+    f, k, rel, hist = orc.solve(G, prm, y, w, f0=f0)
+    fe, rels = f0.copy(), []
+    for _ in range(3):
+        fe, r, _ = dense_outer_iteration(A, geom, y, w, fe, 2, 1, d, W, h, mu)
+        rels.append(r)
+    assert k == 3
+    np.testing.assert_allclose(f, fe, rtol=1e-8, atol=1e-11)
+    np.testing.assert_allclose(hist, rels, rtol=1e-8)
+    assert rel == hist[-1]
+    # from the FBP of all phases: the same iterations from that image
+    f_fbp, k2, _, _ = orc.solve(G, prm, y, w)
+    fe = orc.fbp(G, y)
+    for _ in range(3):
+        fe, _ = orc.step(G, prm, y, w, fe)
+    assert k2 == 3 and np.array_equal(f_fbp, fe)
+
+
+# ----------------------------------------------------------------------- cost
+def test_cost_terms_against_dense_definition(orc):
+    """Eq. 1 with Eq. 2: data = sum (P f - y)^T S^-1 (P f - y) with S^-1 =
+    diag(w) (not its square root); reg = sum_i sum_{j = i+-1} sum_x sum_y
+    w_ij(x, y) (f_i(x) - f_j(y))^2, the weights from the guide, not from f."""
+    geom, A, y, w, f = _dense_problem(23)
+    N, L = geom.n_phases, geom.L
+    d, W, h = 3, 5, 0.015
+    guide = synth.configs.smooth_random_images((N, L, L), 230, passes=1)
+    G = orc.Geometry(geom)
+    prm = orc.params(patch=d, window=W, h=h, mu_hat=1.0)
+    data, reg = orc.cost(G, prm, y, w, f, guide)
+    res = A @ f.ravel() - y.ravel()
+    np.testing.assert_allclose(data, np.sum(w.ravel() * res * res), rtol=1e-12)
+    exp = 0.0
+    for i in range(N):
+        for j in ((i - 1) % N, (i + 1) % N):
+            Om = dense_weights(guide[i], guide[j], d, W, h)
+            diff = f[i].ravel()[:, None] - f[j].ravel()[None, :]
+            exp += np.sum(Om * diff * diff)
+    np.testing.assert_allclose(reg, exp, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------- beta
+def test_power_beta_is_largest_eigenvalue(orc):
+    """beta of Eq. 4: the largest eigenvalue of P_i^T S^-1 P_i, maximised over
+    phases (eigvalsh of the dense matrix). The power estimate never exceeds
+    it and does not decrease with more iterations."""
+    geom = small_geom(N=2, L=6, V=10, B=12)
+    A = dense_P_clip(geom)
+    rng = np.random.default_rng(24)
+    w = rng.uniform(0.5, 2.0, size=(2, 10, 12))
+    w[1] *= 3.0                                        # phase 1 holds the maximum
+    VB, n = 120, 36
+    lam = [np.linalg.eigvalsh(A[i * VB:(i + 1) * VB, i * n:(i + 1) * n].T @
+                              (w[i].ravel()[:, None] * A[i * VB:(i + 1) * VB, i * n:(i + 1) * n]))[-1]
+           for i in range(2)]
+    G = orc.Geometry(geom)
+    est = [orc.power_beta(G, w, k) for k in (2, 5, 30, 400)]
+    assert all(e <= max(lam) * (1 + 1e-12) for e in est)
+    assert all(b >= a * (1 - 1e-12) for a, b in zip(est, est[1:]))
+    assert abs(est[-1] - max(lam)) <= 1e-9 * max(lam)
+    assert lam[1] > lam[0]
+
+
+# ------------------------------------------------------------------------ FBP
+def test_fbp_detector_offset_sign(orc):
+    """The FBP places the bins where the projector puts them: data taken with a
+    quarter-bin detector offset and reconstructed with that offset come out
+    sharper than when reconstructed with the opposite offset (a half-bin
+    error in the back-projection smears every point over a ring)."""
+    import dataclasses
+    geom = synth.ScanGeometry(n_phases=1, L=128, n_views=360, n_bins=256, fov_mm=64.0)
+    obj = [Ellipse(9.0, -6.0, 4.0, 4.0, 0.0, 0.02), Ellipse(-10.0, 8.0, 6.0, 3.0, 0.5, 0.015)]
+    src, u = geom.rays()
+    y = ellipse_line_integrals(src, u, obj)[None]
+    truth = rasterize(obj, geom.L, geom.fov_mm, supersample=8)
+    err = {}
+    for off in (0.25, -0.25):
+        g = dataclasses.replace(geom, det_offset_bins=off)
+        f = orc.fbp(orc.Geometry(g), y)[0]
+        err[off] = np.linalg.norm(f - truth) / np.linalg.norm(truth)
+    assert err[0.25] < 0.8 * err[-0.25], err
+    assert err[0.25] < 0.35, err   # edges of the ellipses limit the error of a band-limited FBP
