@@ -1,21 +1,24 @@
 #!/usr/bin/env python
 """Benchmark of the TNLM 4DCT reconstruction hot path on one MI355X.
 
-Timed step: the 256x256 paper-size slice in its three dose cases, solved
-together as one batch by the batched engine -- FBP of all phases' views, then
-50 outer iterations of (3 CGLS steps -> patch weights over a 15x15 window of
-phases i+-1 with 7x7 patches -> one Gauss-Jacobi sweep -> positivity):
-    a: 360 views/phase, I0 = 2e4     b: 60 views/phase, I0 = 1e6
-    c: 60 views/phase, I0 = 2e4      (10 phases, 512 bins, fan-beam arc)
-Inputs are seeded synthetic phantoms (nested ellipses, moving tumour,
-analytic line integrals, Poisson noise) resident in HBM before timing.
+Timed step: the 64-slice mixed batch solved as one batch by the batched
+engine -- 64 slices x 10 phases, image sides drawn from {128, 256, 384, 512},
+40-360 views per phase, 1.5 L detector bins, I0 log-uniform in [1e4, 1e6];
+FBP of all phases' views, then 50 outer iterations of (3 CGLS steps -> patch
+weights over a 15x15 window of phases i+-1 with 7x7 patches -> one
+Gauss-Jacobi sweep -> positivity), one outer iteration replayed as a captured
+HIP graph. Inputs are seeded synthetic phantoms (nested ellipses, moving
+tumour, analytic line integrals, Poisson noise) resident in HBM before timing.
 
 Metric: phase-pixel*iterations per second = sum over slices of N*L^2*K / wall
-seconds. Also reported: the same workload with BF16-MFMA patch distances,
+seconds. Per-kernel times and the roofline fractions come from a separate,
+untimed pass with per-launch HIP events (which replaces the graph replay by
+direct launches). Also reported: the 256^2 paper-size slice in its three dose
+cases as one batch; 512^2 slices with the FP32 and the BF16-MFMA regulariser;
 and -- when trained warm-start weights are present -- wall seconds per
-10-phase slice to a relative update of 1e-4 for the learned warm start +
-batched engine and for the coarse-to-fine start, against the plain path
-(cold start, one slice at a time).
+10-phase slice to a relative update of 1e-4 on the 32-slice 512^2 evaluation
+set, learned warm start + batched engine and coarse-to-fine start against the
+plain path (cold start, one slice at a time).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -36,6 +39,9 @@ PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # VALU lane-ops/s: 256 CUs x 64 lanes 
 OPS_PER_CROSSING = 8                       # projector: ops per ray-pixel crossing (matrix entry)
 OPS_PER_PAIR = 10                          # regulariser: ops per (pixel, candidate) pair
 WEIGHTS = os.path.join(ROOT, "paper_1009_1351_amd", "weights", "warmstart_c5.npz")
+C3_SLICES = 64
+C5_EVAL_SLICES = 32
+WORKLOAD_KEY = "c3_batch"                  # the workload the stored counter figures were taken on
 
 
 def log(msg):
@@ -56,11 +62,11 @@ def crossings(geom) -> float:
     return float(n.sum())
 
 
-def pairs(case) -> float:
+def pairs(geom, window) -> float:
     """(pixel, candidate) pairs of one regulariser sweep: both neighbours, window truncated to the image."""
-    L, R = case.geom.L, case.window // 2
+    L, R = geom.L, window // 2
     per_axis = sum(min(x + R, L - 1) - max(x - R, 0) + 1 for x in range(L))
-    return 2.0 * case.geom.n_phases * per_axis * per_axis
+    return 2.0 * geom.n_phases * per_axis * per_axis
 
 
 def source_hash(files) -> str:
@@ -78,154 +84,235 @@ KERNEL_SOURCES = {
 }   # a change to these files invalidates the stored traffic figures
 
 
-def traffic_for(kernel: str):
+def traffic_for(kernel: str, workload: str = WORKLOAD_KEY):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source and on this workload; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p)).get(kernel)
     if not rec or rec.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel, [])):
         return None
+    if rec.get("workload") != workload:
+        return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(case_fn):
-    """The FP64 oracle on the host cores: one outer iteration of dose case c
-    (10 phases, 256^2, 60 views x 512 bins) from its FBP start."""
+# ------------------------------------------------------------------- inputs
+def _make(spec):
+    import synth
+    name, s, kw = spec
+    c = synth.make_case(name, slice_index=s, **kw)
+    c.y = np.asarray(c.y, np.float32)
+    c.w = np.asarray(c.w, np.float32)
+    return c
+
+
+def make_cases(specs, workers=None):
+    """Seeded cases for [(config, slice, overrides)], generated in worker
+    processes (before this process touches the GPU); y and w as float32."""
+    n = len(specs)
+    workers = workers or min(16, len(os.sched_getaffinity(0)), n)
+    if workers <= 1 or n <= 1:
+        return [_make(s) for s in specs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_make, specs, chunksize=1)
+
+
+# ---------------------------------------------------------------- baselines
+def cpu_baseline(c3_cases):
+    """The FP64 oracle on the host cores: one outer iteration (FBP start) of
+    two slices of the mixed batch (the smallest-view 128^2 and 256^2 slices),
+    on all the threads this process may use, and of the 128^2 slice on one
+    thread."""
     import oracle
     oracle.build()
-    case = case_fn("C2c")
-    G = oracle.Geometry(case.geom)
-    y = np.asarray(case.y, np.float32).astype(np.float64)
-    w = np.asarray(case.w, np.float32).astype(np.float64)
-    f0 = oracle.fbp(G, y)
-    prm = oracle.case_params(case)
-    t0 = time.perf_counter()
-    oracle.step(G, prm, y, w, f0)
-    dt = time.perf_counter() - t0
-    units = case.geom.n_phases * case.geom.L ** 2
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    threads = min(threads, len(os.sched_getaffinity(0)))
+    from oracle import _lib_threads
+    picks = [c for c in c3_cases if c.name in ("C3/s6", "C3/s34")]
+
+    def run(cases):
+        units, dt = 0, 0.0
+        for case in cases:
+            G = oracle.Geometry(case.geom)
+            y = np.asarray(case.y, np.float64)
+            w = np.asarray(case.w, np.float64)
+            f0 = oracle.fbp(G, y)
+            prm = oracle.case_params(case)
+            t0 = time.perf_counter()
+            oracle.step(G, prm, y, w, f0)
+            dt += time.perf_counter() - t0
+            units += case.geom.n_phases * case.geom.L ** 2
+        return units, dt
+
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0")) or 10**6, len(os.sched_getaffinity(0)))
+    with _lib_threads(threads):
+        units, dt = run(picks)
+    with _lib_threads(1):
+        u1, d1 = run(picks[:1])
+    shapes = ", ".join(f"{c.geom.L}^2 x {c.geom.n_views} views x {c.geom.n_bins} bins" for c in picks)
     return {"value": units / dt, "unit": "phase-pixel*iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"one outer iteration (CGLS x3 + regulariser) of dose case c, 10 x 256^2, 60 views x 512 "
-                      f"bins, from the FBP image; {dt:.1f} s"}
+            "sample": f"one outer iteration (CGLS x3 + regulariser, FBP start) of 2 of the 64 slices ({shapes}); "
+                      f"{dt:.1f} s on {threads} threads",
+            "single_thread": {"value": u1 / d1, "cores": 1,
+                              "sample": f"the {picks[0].geom.L}^2 slice alone, {d1:.1f} s"}}
 
 
-def learned_vs_plain(torch, dev, n_slices, tol=1e-4, restart_after=64):
+# -------------------------------------------------------------------- legs
+def learned_vs_plain(torch, dev, cases, tol=1e-4, restart_after=64):
     """Wall seconds per slice to tol: plain (cold start, one slice at a time)
-    against the learned warm start + batched engine, on 512^2 slices."""
-    import synth
+    against the learned warm start + batched engine, and against the
+    coarse-to-fine start, on the 512^2 evaluation slices (all reported)."""
     from paper_1009_1351_amd import Recon
     from paper_1009_1351_amd.warmstart import LearnedSolver, WarmStartNet
     net = WarmStartNet(phases=10, base=32)
     net.load_weights(WEIGHTS)
-    cases = [synth.make_case("C5eval", slice_index=20_000 + k) for k in range(n_slices)]
+    n_slices = len(cases)
     c0 = cases[0]
     prm = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat)
-    ys = [torch.from_numpy(np.asarray(c.y, np.float32)).to(dev) for c in cases]
-    ws = [torch.from_numpy(np.asarray(c.w, np.float32)).to(dev) for c in cases]
+    ys = [torch.from_numpy(c.y).to(dev) for c in cases]
+    ws = [torch.from_numpy(c.w).to(dev) for c in cases]
     plain = [Recon.from_geometry(c.geom, max_outer=c0.max_outer, tol=tol, device=dev, **prm) for c in cases]
     solver = LearnedSolver([c.geom for c in cases], net, tol=tol, max_outer=c0.max_outer, restart_after=restart_after,
                            device=dev, **prm)
-    plain[0].solve(ys[0], ws[0])   # warm-up of both paths
-    solver.solve(ys, ws)
+    plain[0].solve(ys[0], ws[0])   # warm-up: library kernels loaded
+    net.forward(torch.zeros((1, 10, c0.geom.L, c0.geom.L), device=dev), factor=net.factor_for(c0.geom.L))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = [rc.solve(y, w) for rc, y, w in zip(plain, ys, ws)]
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    log("  plain done")
     t0 = time.perf_counter()
-    _, it_l, st_l, used = solver.solve(ys, ws)
+    _, it_l, st_l, used, probe = solver.solve(ys, ws, with_probe=True)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     solver.close()
+    log("  learned done")
     from paper_1009_1351_amd.multigrid import MultigridSolver
     mg = MultigridSolver([c.geom for c in cases], tol=tol, max_outer=c0.max_outer, restart_after=restart_after,
                          device=dev, **prm)
-    mg.solve(ys, ws)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, it_m, it_mc, st_m = mg.solve(ys, ws)
     torch.cuda.synchronize()
     t_mg = time.perf_counter() - t0
     mg.close()
+    log("  coarse-to-fine done")
     return {"workload": f"{n_slices} slices x 10 phases, 512^2, 60 views x 720 bins, I0 2e4, h_rel 0.6, "
-                        f"to relative update {tol} (cap {c0.max_outer})",
+                        f"to relative update {tol} (cap {c0.max_outer}); slices {cases[0].name}..{cases[-1].name}",
             "plain_wall_s_per_slice": t_plain / n_slices, "plain_iters": [r[1] for r in res],
             "learned_batched_wall_s_per_slice": t_learned / n_slices, "learned_iters": it_l,
-            "warm_start_used": int(sum(used)), "plain_reached_tol": int(sum(r[3] == 0 for r in res)),
+            "learned_probe_iters": probe, "warm_start_used": int(sum(used)),
+            "plain_reached_tol": int(sum(r[3] == 0 for r in res)),
             "learned_reached_tol": int(sum(s_ == 0 for s_ in st_l)), "speedup": t_plain / t_learned,
             "multigrid_wall_s_per_slice": t_mg / n_slices, "multigrid_iters": it_m, "multigrid_coarse_iters": it_mc,
             "multigrid_reached_tol": int(sum(s_ == 0 for s_ in st_m)), "multigrid_speedup": t_plain / t_mg}
 
 
-def batched_legs(torch, dev, n_c3, n_c4, iters=10):
-    """Optional legs on the batched and precision workloads: a ragged batch of
-    n_c3 slices (L from {128..512}, 40-360 views, B = 1.5 L) solved as one
-    batch (graph replay, no per-kernel events) against the same slices solved
-    one at a time; and n_c4 slices at 512^2 (720 bins, 120 views) with the
-    FP32 and the BF16-MFMA regulariser."""
-    import synth
-    from paper_1009_1351_amd import Batch, Recon
-    out = {}
+def c2_leg(torch, dev, cases, steps=3):
+    """The 256^2 paper-size slice in its three dose cases as one batch, 50
+    outer iterations (graph replay)."""
+    from paper_1009_1351_amd import Batch
+    c0 = cases[0]
+    bt = Batch([c.geom for c in cases], patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat,
+               max_outer=c0.max_outer, tol=0.0, device=dev)
+    ys = [torch.from_numpy(c.y).to(dev) for c in cases]
+    ws = [torch.from_numpy(c.w).to(dev) for c in cases]
+    fs = bt.new_images()
+    bt.solve(ys, ws, fs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    units = 0
+    for _ in range(steps):
+        _, iters, _, _, _ = bt.solve(ys, ws, fs)
+        units += sum(c.geom.n_phases * c.geom.L ** 2 * k for c, k in zip(cases, iters))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bt.close()
+    return {"workload": "3 slices x 10 phases, 256^2, 512 bins, doses a (360 views, I0 2e4), b (60 views, I0 1e6), "
+                        "c (60 views, I0 2e4) in one batch; 50 outer iterations",
+            "value": units / dt, "ms_per_solve": dt / steps * 1e3}
 
-    def arrays(cases):
-        return ([torch.from_numpy(c.y.astype(np.float32)).to(dev) for c in cases],
-                [torch.from_numpy(c.w.astype(np.float32)).to(dev) for c in cases])
 
-    def make(name, n):
-        cases = []
-        for s in range(n):
-            cases.append(synth.make_case(name, slice_index=s, K=iters))
-            if (s + 1) % 8 == 0 or s + 1 == n:
-                log(f"{name}: {s + 1}/{n} slices generated")
-        return cases
-
-    if n_c3:
-        cases = make("C3", n_c3)
-        ys, ws = arrays(cases)
-        kw = dict(patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat, max_outer=iters, tol=0.0, device=dev)
-        units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
-        bt = Batch([c.geom for c in cases], **kw)
+def precision_leg(torch, dev, cases):
+    """512^2 slices (120 views x 720 bins) with the FP32 and the BF16-MFMA
+    regulariser, 10 outer iterations each."""
+    from paper_1009_1351_amd import Batch
+    ys = [torch.from_numpy(c.y).to(dev) for c in cases]
+    ws = [torch.from_numpy(c.w).to(dev) for c in cases]
+    iters = cases[0].max_outer
+    units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
+    res = {}
+    for mode in ("fp32", "bf16_mfma"):
+        bt = Batch([c.geom for c in cases], patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat,
+                   max_outer=iters, tol=0.0, ssd_mode=mode, device=dev)
         bt.solve(ys, ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bt.solve(ys, ws)
         torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        bt.timing(True)
+        bt.solve(ys, ws)
+        t = bt.timing_read()
         bt.close()
-        rcs = [Recon.from_geometry(c.geom, **kw) for c in cases]
-        rcs[0].solve(ys[0], ws[0])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for rc, y, w in zip(rcs, ys, ws):
-            rc.solve(y, w)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        log(f"C3: batched {tb:.2f} s, one at a time {tp:.2f} s")
-        out["batched_c3"] = {"slices": n_c3, "iters": iters, "shapes": [[c.geom.L, c.geom.n_views, c.geom.n_bins]
-                                                                        for c in cases],
-                             "batched_value": units / tb, "one_at_a_time_value": units / tp, "unit": "phase-pixel*iters/s"}
-    if n_c4:
-        cases = make("C4", n_c4)
-        ys, ws = arrays(cases)
-        res = {}
-        for mode in ("fp32", "bf16_mfma"):
-            bt = Batch([c.geom for c in cases], patch=7, window=15, h=cases[0].h, mu_hat=cases[0].mu_hat,
-                       max_outer=iters, tol=0.0, ssd_mode=mode, device=dev)
-            bt.solve(ys, ws)
-            bt.timing(True)
-            t0 = time.perf_counter()
-            bt.solve(ys, ws)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            t = bt.timing_read()
-            bt.close()
-            units = sum(c.geom.n_phases * c.geom.L ** 2 * iters for c in cases)
-            res[mode] = {"value": units / dt, "regularize_ms_per_launch": t["regularize"][0] / max(t["regularize"][1], 1)}
-        out["precision_c4"] = {"slices": n_c4, "iters": iters, **res}
-    return out
+        res[mode] = {"value": units / dt,
+                     "regularize_ms_per_launch": round(t["regularize"][0] / max(t["regularize"][1], 1), 4)}
+    return {"workload": f"{len(cases)} slices x 10 phases, 512^2, 120 views x 720 bins, I0 5e4, {iters} iterations",
+            **res, "bf16_over_fp32_regularize": round(res["bf16_mfma"]["regularize_ms_per_launch"] /
+                                                      res["fp32"]["regularize_ms_per_launch"], 3)}
+
+
+def cnn_flops(phases, base, H, W):
+    """Multiply-add FLOPs (2 per MAC) of one forward pass of the warm-start
+    network on one [phases][H][W] input: (in, out, kernel, grid divisor) of
+    each convolution, encoder 4 levels, decoder with skip concatenation, 1x1
+    output."""
+    b, P = base, phases
+    layers = [(P, b, 3, 1), (b, b, 3, 1), (b, 2 * b, 3, 2), (2 * b, 2 * b, 3, 2), (2 * b, 4 * b, 3, 4),
+              (4 * b, 4 * b, 3, 4), (4 * b, 8 * b, 3, 8), (8 * b, 8 * b, 3, 8), (12 * b, 4 * b, 3, 4),
+              (4 * b, 4 * b, 3, 4), (6 * b, 2 * b, 3, 2), (2 * b, 2 * b, 3, 2), (3 * b, b, 3, 1), (b, b, 3, 1),
+              (b, P, 1, 1)]
+    return sum(2.0 * ci * co * k * k * (H // d) * (W // d) for ci, co, k, d in layers)
+
+
+def cnn_leg(torch, dev, n_fwd=8, n_train=8, L=256, reps=5):
+    """Throughput of the warm-start network's BF16 MFMA convolutions: forward
+    passes of n_fwd inputs at L^2 and Adam training steps (forward, data and
+    weight gradients) on n_train pairs, against the dense BF16 MFMA peak."""
+    from paper_1009_1351_amd.warmstart import WarmStartNet
+    net = WarmStartNet(phases=10, base=32, seed=1, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    x = (0.02 * torch.rand((max(n_fwd, n_train), 10, L, L), generator=g)).to(dev)
+    t = (0.02 * torch.rand((n_train, 10, L, L), generator=g)).to(dev)
+    xf = x[:n_fwd].contiguous()
+    xt = x[:n_train].contiguous()
+    out = torch.empty_like(xf)
+    net.forward(xf, out)
+    net.train_step(xt, t, 1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(xf, out)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(xt, t, 1e-5)
+    torch.cuda.synchronize()
+    t_tr = (time.perf_counter() - t0) / reps
+    net.close()
+    ff = cnn_flops(10, 32, L, L)
+    peak = 2500.0
+    fwd_tf = n_fwd * ff / t_fwd / 1e12
+    tr_tf = 3 * n_train * ff / t_tr / 1e12
+    return {"workload": f"forward of {n_fwd} x 10 x {L}^2, Adam step on {n_train} pairs at {L}^2 (bf16 MFMA, fp32 "
+                        "accumulate); flops = 2 per MAC of the convolutions, training step counted as 3 forwards",
+            "forward_ms": round(t_fwd * 1e3, 3), "forward_tflops": round(fwd_tf, 2),
+            "train_step_ms": round(t_tr * 1e3, 3), "train_tflops": round(tr_tf, 2),
+            "roofline": {"bound": "mfma", "peak": peak, "unit": "TFLOP/s", "forward_frac": round(fwd_tf / peak, 4),
+                         "train_frac": round(tr_tf / peak, 4)}}
 
 
 def omega_star_leg(torch, dev, iters=50):
@@ -278,6 +365,7 @@ def quality_leg(torch, dev, iters=50):
     return {"iters": iters, "cases": out}
 
 
+# ------------------------------------------------------- profile summaries
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
            "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
 
@@ -289,24 +377,25 @@ def kind_of(name):
     return None
 
 
+def _one(d, pat):
+    import glob
+    f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+    if not f:
+        raise SystemExit(f"no {pat} under {d}")
+    return f[0]
+
+
 def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, bench_json):
-    """Write profiles/kernels_c2_batch.md, profiles/traffic_c2_batch.md and
+    """Write profiles/kernels_c3_batch.md, profiles/traffic_c3_batch.md and
     profiles/traffic.json from rocprofv3 CSV output (kernel stats, and two
     counter runs: FETCH_SIZE, WRITE_SIZE, in KiB per dispatch)."""
     import csv
-    import glob
     from collections import defaultdict
 
-    def one(d, pat):
-        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
-        if not f:
-            raise SystemExit(f"no {pat} under {d}")
-        return f[0]
-
-    rows = list(csv.DictReader(open(one(kt_dir, "*kernel_stats.csv"))))
+    rows = list(csv.DictReader(open(_one(kt_dir, "*kernel_stats.csv"))))
     bj = json.loads(open(bench_json).read().strip().splitlines()[-1])
-    out = ["# Kernel time, C2 batch (3 slices x 10 phases, 256^2, one batched solve per step)", "",
-           "Command (repository root):", "", "    " + command, "",
+    out = ["# Kernel time, 64-slice mixed batch (L 128-512, 40-360 views, B 1.5 L; one batched 50-iteration "
+           "solve per step)", "", "Command (repository root):", "", "    " + command, "",
            "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
     for r in rows[:16]:
         out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
@@ -317,20 +406,22 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
         if k:
             kind_ns[k][0] += float(r["TotalDurationNs"])
             kind_ns[k][1] += int(r["Calls"])
-    out += ["", "Average per launch by kind (all template instances), against the HIP-event figure "
+    out += ["", "Average per launch by kind (all template instances), against the HIP-event figures "
                 "that bench.py measured in the same run:", "",
-            "| kind | launches | avg ms (trace) |", "|---|---|---|"]
+            "| kind | launches | avg ms (trace) | avg ms (HIP events) |", "|---|---|---|---|"]
+    rk = bj.get("roofline_kernels", {})
     for k, (ns, n) in sorted(kind_ns.items()):
-        out.append(f"| {k} | {n} | {ns / n / 1e6:.4f} |")
+        ev = rk.get(k, {}).get("avg_launch_ms")
+        out.append(f"| {k} | {n} | {ns / n / 1e6:.4f} | {ev if ev is not None else '-'} |")
     rf = bj.get("roofline", {})
     out += ["", f"bench.py roofline kernel: {rf.get('kernel')}, avg launch {rf.get('avg_launch_ms')} ms "
                 f"(HIP events), frac {rf.get('frac')} of {rf.get('peak')} {rf.get('unit')}.", "",
             "The bench line of that run:", "", "    " + json.dumps(bj), ""]
-    open(os.path.join(ROOT, "profiles", "kernels_c2_batch.md"), "w").write("\n".join(out))
+    open(os.path.join(ROOT, "profiles", "kernels_c3_batch.md"), "w").write("\n".join(out))
 
     def counters(d):
         per = defaultdict(list)
-        for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
+        for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
             per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return per
 
@@ -338,7 +429,7 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
     copy_bytes = 64 * 1024 * 1024 * 4
     cf = copy_bytes / 1024 / max(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)
     cw = copy_bytes / 1024 / max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
-    out = ["# HBM traffic per dispatch, C2 batch", "",
+    out = ["# HBM traffic per dispatch, 64-slice mixed batch", "",
            "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two counter runs:", "",
            "    " + counters_command.replace("COUNTER", "FETCH_SIZE").replace("DIR", "fetch"),
            "    " + counters_command.replace("COUNTER", "WRITE_SIZE").replace("DIR", "write"), "",
@@ -361,52 +452,80 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
     tj = {}
     for kd, (b, n) in by_kind.items():
         if kd in KERNEL_SOURCES:
-            tj[kd] = {"source_hash": source_hash(KERNEL_SOURCES[kd]), "bytes_per_launch": b / n}
-    out += ["", "Per kind (dispatch-weighted mean, scaled bytes): " +
-            ", ".join(f"{k} {v['bytes_per_launch'] / 1e6:.2f} MB" for k, v in sorted(tj.items())), ""]
-    open(os.path.join(ROOT, "profiles", "traffic_c2_batch.md"), "w").write("\n".join(out))
+            tj[kd] = {"source_hash": source_hash(KERNEL_SOURCES[kd]), "workload": WORKLOAD_KEY,
+                      "bytes_per_launch": b / n}
+    alg = {k: v.get("algorithmic_bytes_per_launch") for k, v in rk.items()}
+    out += ["", "Per kind (dispatch-weighted mean, scaled bytes) against the algorithmic bytes per launch "
+                "that bench.py counts:", "", "| kind | counted MB / launch | algorithmic MB / launch | ratio |",
+            "|---|---|---|---|"]
+    for k, v in sorted(tj.items()):
+        a_ = alg.get(k)
+        out.append(f"| {k} | {v['bytes_per_launch'] / 1e6:.2f} | {a_ / 1e6 if a_ else float('nan'):.2f} | "
+                   f"{v['bytes_per_launch'] / a_ if a_ else float('nan'):.2f} |")
+    out.append("")
+    open(os.path.join(ROOT, "profiles", "traffic_c3_batch.md"), "w").write("\n".join(out))
     json.dump(tj, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
 
 
-def summarize_bf16(kt_dir, command):
-    """profiles/regularize_bf16_c2_batch.md: FP32 and BF16-MFMA regulariser
-    kernels of one traced run of both bench legs."""
+def summarize_counters(out_md, title, command, dirs):
+    """A counter table (per kernel kind: mean per dispatch of each counter)
+    from one or more rocprofv3 --pmc runs, written to profiles/<out_md>."""
     import csv
-    import glob
-    f = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
-    rows = [r for r in csv.DictReader(open(f)) if kind_of(r["Name"]) in ("regularize", "regularize_bf16")]
-    out = ["# Regulariser: FP32 box sums against BF16 MFMA patch distances, C2 batch", "",
-           "Command (repository root):", "", "    " + command, "",
-           "| kernel | calls | avg us |", "|---|---|---|"]
-    for r in rows:
-        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} |")
-    avg = {kind_of(r["Name"]): float(r["AverageNs"]) for r in rows}
-    if "regularize" in avg and "regularize_bf16" in avg:
-        out += ["", f"BF16 MFMA / FP32 time per launch: {avg['regularize_bf16'] / avg['regularize']:.2f}", ""]
-    open(os.path.join(ROOT, "profiles", "regularize_bf16_c2_batch.md"), "w").write("\n".join(out))
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+            k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
+            if k:
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in vals for c in vals[k]})
+    out = [f"# {title}", "", "Commands (repository root):", ""] + ["    " + c for c in command.split(" ;; ")] + [
+        "", "Mean per dispatch:", "", "| kind | dispatches | " + " | ".join(names) + " |",
+        "|---|---|" + "---|" * len(names)]
+    for k in sorted(vals):
+        n = max(len(v) for v in vals[k].values())
+        cells = [f"{np.mean(vals[k][c]):.4g}" if vals[k].get(c) else "-" for c in names]
+        out.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    out.append("")
+    open(os.path.join(ROOT, "profiles", out_md), "w").write("\n".join(out))
+
+
+# --------------------------------------------------------------------- main
+def roofline_entry(kind, ms_tot, launches, ops_per_launch, bytes_per_launch):
+    achieved = ops_per_launch * launches / (ms_tot * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": kind, "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
+            "avg_launch_ms": round(ms_tot / max(launches, 1), 4), "launches": launches,
+            "algorithmic_ops_per_launch": ops_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "traffic": traffic_for(kind)}
 
 
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] == "summarize-bf16":
-        summarize_bf16(sys.argv[2], sys.argv[3])
-        return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize":
         # bench.py summarize KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON "COMMAND" "COUNTERS_COMMAND"
         # (COUNTERS_COMMAND with COUNTER and DIR standing for the counter and its output folder)
         summarize_profiles(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[6], sys.argv[7], sys.argv[5])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
+        # bench.py summarize-counters OUT_MD "TITLE" "COMMANDS (;; separated)" DIR [DIR ...]
+        summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=50, help="outer iterations per solve")
+    ap.add_argument("--slices", type=int, default=C3_SLICES, help="slices of the mixed batch (64 = the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and warm-start legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the C2, precision and warm-start legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the warm-start leg")
-    ap.add_argument("--learned-slices", type=int, default=4)
+    ap.add_argument("--no-timing-pass", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--learned-slices", type=int, default=C5_EVAL_SLICES)
+    ap.add_argument("--ssd-mode", default="fp32", choices=("fp32", "bf16_mfma"),
+                    help="patch distances of the timed batch (the workload is fp32)")
+    ap.add_argument("--cnn", action="store_true", help="run only the network leg (for profiling)")
+    ap.add_argument("--gen-workers", type=int, default=0, help="input generation processes (0: one per core, <= 16)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
-    ap.add_argument("--c3", type=int, default=0, help="also run a ragged batch of this many slices")
-    ap.add_argument("--c4", type=int, default=0, help="also run this many 512^2 slices with both SSD modes")
     ap.add_argument("--omega-star", action="store_true", help="also compare adaptive and phantom-derived weights")
     ap.add_argument("--quality", action="store_true", help="also report CNR and SNR of FBP and TNLM images")
     a = ap.parse_args()
@@ -415,92 +534,113 @@ def main():
                                    "(slices would shard across GPUs without communication)"}))
         sys.exit(2)
 
+    if a.cnn:
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        print(json.dumps({"cnn": cnn_leg(torch, dev)}), flush=True)
+        return
+    # inputs first, in worker processes, before anything touches the GPU
+    t_gen = time.perf_counter()
+    specs = [("C3", s, dict(K=a.iters)) for s in range(a.slices)]
+    extras = not a.no_extras
+    learned = extras and not a.no_learned and os.path.exists(WEIGHTS)
+    if extras:
+        specs += [(n, 0, {}) for n in ("C2a", "C2b", "C2c")] + [("C4", s, dict(K=10)) for s in range(4)]
+    if learned:
+        specs += [("C5eval", 20_000 + k, {}) for k in range(a.learned_slices)]
+    allc = make_cases(specs, a.gen_workers or None)
+    cases = allc[:a.slices]
+    c2 = allc[a.slices:a.slices + 3] if extras else []
+    c4 = allc[a.slices + 3:a.slices + 7] if extras else []
+    c5 = allc[a.slices + 7:] if learned else []
+    log(f"inputs generated ({len(allc)} slices, {time.perf_counter() - t_gen:.1f} s)")
+
     import torch
-    import synth
     from paper_1009_1351_amd import Batch
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    names = ["C2a", "C2b", "C2c"]
-    cases = [synth.make_case(n, K=a.iters) for n in names]
-    log("inputs generated")
     c0 = cases[0]
     kw = dict(patch=c0.patch, window=c0.window, h=c0.h, mu_hat=c0.mu_hat, m1=c0.m1, m2=c0.m2, max_outer=a.iters,
-              tol=0.0, device=dev)
+              tol=0.0, ssd_mode=a.ssd_mode, device=dev)
     bt = Batch([c.geom for c in cases], **kw)
-    ys = [torch.from_numpy(c.y.astype(np.float32)).to(dev) for c in cases]
-    ws = [torch.from_numpy(c.w.astype(np.float32)).to(dev) for c in cases]
+    ys = [torch.from_numpy(c.y).to(dev) for c in cases]
+    ws = [torch.from_numpy(c.w).to(dev) for c in cases]
     fs = bt.new_images()
     torch.cuda.synchronize()
 
-    def step(b):
-        _, iters, _, st, _ = b.solve(ys, ws, fs)
+    def step():
+        _, iters, _, st, _ = bt.solve(ys, ws, fs)
         return sum(c.geom.n_phases * c.geom.L ** 2 * k for c, k in zip(cases, iters))
 
-    for _ in range(a.warmup):
-        step(bt)
-    log("warmup done")
+    for s in range(a.warmup):
+        step()
+        log(f"warmup {s + 1}/{a.warmup}")
     if a.calib_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    bt.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     units = 0
     for s in range(a.steps):
-        units += step(bt)
+        units += step()
         log(f"step {s + 1}/{a.steps}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    t = bt.timing_read()
-    bt.timing(False)
-    per_kind = {k: list(v) for k, v in t.items()}
-    nz = sum(crossings(c.geom) for c in cases)
-    npairs = sum(pairs(c) for c in cases)
-    algo = {"project": t["project"][1] * nz * OPS_PER_CROSSING,
-            "backproject": t["backproject"][1] * nz * OPS_PER_CROSSING,
-            "regularize": t["regularize"][1] * npairs * OPS_PER_PAIR}
-    dom = max(algo, key=lambda k: per_kind[k][0])
-    ms_tot, launches = per_kind[dom]
-    achieved = algo[dom] / (ms_tot * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
-            "unit": "TOP/s", "frac": round(achieved / PEAK_ALU_TOPS, 4),
-            "avg_launch_ms": round(ms_tot / max(launches, 1), 4),
-            "algorithmic_ops_per_launch": algo[dom] / max(launches, 1),
-            "traffic": traffic_for(dom)}
     value = units / dt
     slices = len(cases) * a.steps
     out = {
         "metric": "phase-pixel*iters/s", "value": value, "unit": "phase-pixel*iters/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "C2: 3 slices x 10 phases, 256x256, 512 bins, doses a (360 views, I0 2e4), "
-                               "b (60 views, I0 1e6), c (60 views, I0 2e4) in one batch; patch 7, window 15, "
-                               f"M1 3, M2 1; {a.iters} outer iterations from the FBP of all phases",
-                   "slices_per_step": len(cases), "wall_s_per_slice": dt / slices, "parallelism": "single GPU"},
-        "kernel_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in per_kind.items()},
-        "roofline": roof,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.ssd_mode == "fp32" else "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"mixed batch: {len(cases)} slices x 10 phases, L from {{128,256,384,512}}, 40-360 "
+                               "views, 1.5 L bins, I0 1e4-1e6; patch 7, window 15, M1 3, M2 1; "
+                               f"{a.iters} outer iterations from the FBP of all phases, one batched solve per step "
+                               "(one outer iteration replayed as a HIP graph)",
+                   "slices_per_step": len(cases), "wall_s_per_slice": dt / slices,
+                   "phase_pixel_iters_per_step": units // max(a.steps, 1), "parallelism": "single GPU"},
     }
-    if not a.no_extras:
-        log("BF16-MFMA leg ...")
-        bb = Batch([c.geom for c in cases], ssd_mode="bf16_mfma", **kw)
-        step(bb)
-        torch.cuda.synchronize()
-        bb.timing(True)
-        t0 = time.perf_counter()
-        u = step(bb)
-        torch.cuda.synchronize()
-        d2 = time.perf_counter() - t0
-        tb = bb.timing_read()
-        out["bf16_mfma"] = {"value": u / d2, "regularize_ms_per_step": round(tb["regularize"][0], 3),
-                            "fp32_regularize_ms_per_step": round(per_kind["regularize"][0] / a.steps, 3)}
-        bb.close()
-        if os.path.exists(WEIGHTS) and not a.no_learned:
-            log("learned warm start leg ...")
-            out["learned_vs_plain"] = learned_vs_plain(torch, dev, a.learned_slices)
+    if not a.no_timing_pass:
+        log("per-kernel timing pass ...")
+        bt.timing(True)
+        step()
+        t = bt.timing_read()
+        bt.timing(False)
+        per_kind = {k: list(v) for k, v in t.items()}
+        nz = sum(crossings(c.geom) for c in cases)
+        npairs = sum(pairs(c.geom, c.window) for c in cases)
+        nimg = sum(c.geom.n_phases * c.geom.L ** 2 for c in cases)
+        nsino = sum(c.geom.n_phases * c.geom.n_views * c.geom.n_bins for c in cases)
+        # algorithmic bytes per launch (FP32): projector reads the image and its
+        # transposed copy and writes q (the residual launch also reads y and
+        # sqrt(w) and writes r and sqrt(w) r); back-projector reads q and writes
+        # the image; regulariser reads guide/value/g once and writes the output
+        algo_bytes = {"project": 4.0 * (2 * nimg + 1.5 * nsino), "backproject": 4.0 * (nimg + nsino),
+                      "regularize": 4.0 * 2 * nimg}
+        algo_ops = {"project": nz * OPS_PER_CROSSING, "backproject": nz * OPS_PER_CROSSING,
+                    "regularize": npairs * OPS_PER_PAIR}
+        rk = {k: roofline_entry(k, per_kind[k][0], per_kind[k][1], algo_ops[k], algo_bytes[k])
+              for k in algo_ops if per_kind[k][1]}
+        dom = max(rk, key=lambda k: per_kind[k][0])
+        out["roofline"] = rk[dom]
+        out["roofline_kernels"] = rk
+        out["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in per_kind.items()}
+        out["kernel_ms_note"] = "one solve with per-launch HIP events (direct launches, no graph replay)"
+    if extras:
+        log("C2 leg ...")
+        out["c2_batch"] = c2_leg(torch, dev, c2)
+        log("precision leg ...")
+        out["bf16_mfma"] = precision_leg(torch, dev, c4)
+        log("network leg ...")
+        out["cnn"] = cnn_leg(torch, dev)
+        if learned:
+            log(f"learned warm start leg ({len(c5)} slices) ...")
+            out["learned_vs_plain"] = learned_vs_plain(torch, dev, c5)
         else:
             out["learned_vs_plain"] = None
     if a.quality:
@@ -509,12 +649,9 @@ def main():
     if a.omega_star:
         log("fixed-weight reference ...")
         out["omega_star"] = omega_star_leg(torch, dev)
-    if a.c3 or a.c4:
-        log("batched / precision legs ...")
-        out.update(batched_legs(torch, dev, a.c3, a.c4))
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(lambda n: synth.make_case(n, K=a.iters))
+        out["cpu_baseline"] = cpu_baseline(cases)
     print(json.dumps(out), flush=True)
 
 

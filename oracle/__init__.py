@@ -8,6 +8,7 @@ view angles) and NumPy float64 arrays.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -27,6 +28,18 @@ def build(force: bool = False) -> str:
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
+
+
+@contextlib.contextmanager
+def _lib_threads(n: int):
+    """Run the oracle's OpenMP loops on n threads inside the block."""
+    L = lib()
+    prev = L.omp_get_max_threads()
+    L.omp_set_num_threads(int(n))
+    try:
+        yield
+    finally:
+        L.omp_set_num_threads(prev)
 
 
 class _Geom(C.Structure):

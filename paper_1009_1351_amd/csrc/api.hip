@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <fstream>
 #include <memory>
 #include <new>
@@ -439,9 +440,10 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         // slice's crossings over its blocks: ray lengths and the share of a
         // slice's last bin block that holds rays differ between slices); a
         // back-projector tile runs V views of a ~40-operation set-up plus
-        // ~14 operations per candidate bin, ~1.5 + B D / (fan * SAD) bins
-        kfp.push_back(crossings[&d - E.sl.data()] / std::max(1, proj_blocks(d)));
-        const double cand = 1.5 + d.B * (double)d.D / (d.B * (double)d.dgamma * 541.0);
+        // ~14 operations per candidate bin, ~1.5 + D / (dgamma * SAD) bins
+        const size_t si = (size_t)(&d - E.sl.data());
+        kfp.push_back(crossings[si] / std::max(1, proj_blocks(d)));
+        const double cand = 1.5 + (double)d.D / ((double)d.dgamma * E.geoms[si].sad_mm);
         kbp.push_back(d.V * (40.0 + 14.0 * cand));
         cvec.push_back(d.N * vec_blocks(d));
         creg.push_back(d.nrb);
@@ -818,10 +820,9 @@ static tnlm_status engine_autotune(Engine *E, int *chosen, float *ms_out) {
     }
     const std::string path = tune_cache_path();
     const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        const std::string dir = path.substr(0, slash);
-        std::string cmd = "mkdir -p '" + dir + "'";
-        if (std::system(cmd.c_str()) != 0) { /* cache is best effort */ }
+    if (slash != std::string::npos && slash > 0) {   // the cache is best effort: errors leave it unwritten
+        std::error_code ec;
+        std::filesystem::create_directories(path.substr(0, slash), ec);
     }
     std::ofstream fo(path, std::ios::app);
     if (fo)

@@ -279,10 +279,15 @@ class LearnedSolver:
                                    max_outer=max_outer - WARM_START_ITERS, restart_after=restart_after,
                                    stall_window=stall_window, stall_ratio=stall_ratio, device=device)
 
-    def solve(self, ys, ws):
+    def solve(self, ys, ws, with_probe=False):
+        """Returns (images, iterations, statuses, used_warm); iterations count
+        the kept start's WARM_START_ITERS and those after it. The fallback
+        check also runs WARM_START_ITERS iterations from the start it rejects:
+        with_probe=True appends those per slice as a fifth element."""
         fs, used = warm_starts(self.inner.recons, ys, ws, self.net)
         fs, it, st = self.inner.solve(ys, ws, fs)
-        return fs, [WARM_START_ITERS + k for k in it], st, used
+        out = (fs, [WARM_START_ITERS + k for k in it], st, used)
+        return out + ([WARM_START_ITERS] * self.n,) if with_probe else out
 
     def close(self):
         self.inner.close()
