@@ -38,7 +38,8 @@ def test_crossing_count_matches_traced_rays(orc):
 
 def test_traffic_figure_only_for_the_profiled_source(tmp_path, monkeypatch):
     """The bench line's HBM traffic comes from the stored counter summary only
-    while the kernel's sources hash to the value recorded with it; any change
+    while it was taken on the benchmark's workload and the kernel's sources
+    hash to the value recorded with it; any change
     to them (a comment included) makes it null until the counters are taken
     again."""
     sys.path.insert(0, ROOT)
@@ -52,6 +53,12 @@ def test_traffic_figure_only_for_the_profiled_source(tmp_path, monkeypatch):
     assert bench.traffic_for("project") is None   # no summary stored
     (tmp_path / "profiles").mkdir()
     rec = {"project": {"source_hash": bench.source_hash(files), "bytes_per_launch": 1.25e8}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.traffic_for("project") is None   # taken on no named workload
+    rec["project"]["workload"] = "another workload"
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.traffic_for("project") is None   # taken on another workload
+    rec["project"]["workload"] = bench.WORKLOAD_KEY
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     assert bench.traffic_for("project") == 1.25e8
     assert bench.traffic_for("regularize") is None   # no record for this kernel
