@@ -307,6 +307,26 @@ tnlm_status tnlm_cnn_save(tnlm_cnn *net, const char *path);
 tnlm_status tnlm_cnn_load(tnlm_cnn *net, const char *path);
 const char *tnlm_cnn_last_error(void);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweep of
+ * tnlm_regularize for one slice of n_phases x L x L without a context. Same
+ * arithmetic and the same bits as tnlm_regularize with (patch, window, h,
+ * mu_hat) of a context of that slice. Stacks [n_phases][L][L] float32 on the
+ * current device; d_out must not alias the inputs; enqueued on `stream`
+ * (hipStream_t as void*, on the current device). Async.
+ * No device or host allocation: the kernel's tables (slice descriptor and
+ * work ranges) are written into a library-owned device array of 1 KiB per GPU,
+ * held until the process ends. Every call on a GPU reuses that array, so
+ * calls that may overlap on one GPU (different streams, or threads) race and
+ * must be ordered by the caller. Sizes as tnlm_recon_init accepts them:
+ * 1 <= L <= 4096, n_phases * L^2 <= 2^31 (else TNLM_E_SHAPE), window <= L,
+ * patch odd in [3, 9], window odd in [3, 21].
+ */
+tnlm_status tnlm_regularize_noalloc(int32_t n_phases, int32_t L, int32_t patch, int32_t window, float h,
+                                   float mu_hat, const float *d_guide, const float *d_value, const float *d_g,
+                                   float *d_out, int32_t clamp, void *stream);
+
 const char *tnlm_status_string(tnlm_status s);
 const char *tnlm_last_error(void);
 

@@ -50,6 +50,8 @@ for _name, _args, _res in [
     ("tnlm_fbp", [_P, _P, _P, C.c_int32], C.c_int),
     ("tnlm_data_step", [_P, _P, _P, _P, _P], C.c_int),
     ("tnlm_regularize", [_P, _P, _P, _P, _P, C.c_int32], C.c_int),
+    ("tnlm_regularize_noalloc", [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, _P, _P, _P, _P,
+                                 C.c_int32, _P], C.c_int),
     ("tnlm_timing_enable", [_P, C.c_int32], C.c_int),
     ("tnlm_timing_read", [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)], C.c_int),
     ("tnlm_autotune", [_P, C.POINTER(C.c_int32), _FP], C.c_int),
@@ -90,7 +92,7 @@ for _name, _args, _res in [
 
 def exported_symbols():
     return ["tnlm_recon_init", "tnlm_destroy", "tnlm_step", "tnlm_solve", "tnlm_get_history", "tnlm_project",
-            "tnlm_backproject", "tnlm_fbp", "tnlm_data_step", "tnlm_regularize", "tnlm_timing_enable",
+            "tnlm_backproject", "tnlm_fbp", "tnlm_data_step", "tnlm_regularize", "tnlm_regularize_noalloc", "tnlm_timing_enable",
             "tnlm_timing_read", "tnlm_autotune", "tnlm_batch_init", "tnlm_batch_destroy", "tnlm_batch_solve", "tnlm_batch_solve_active",
             "tnlm_batch_timing_enable", "tnlm_batch_timing_read", "tnlm_data_cost", "tnlm_cost", "tnlm_rel_change", "tnlm_set_guide", "tnlm_image_upsample", "tnlm_cnn_create",
             "tnlm_cnn_destroy", "tnlm_cnn_num_params", "tnlm_cnn_get_params", "tnlm_cnn_set_params",

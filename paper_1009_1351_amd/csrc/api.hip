@@ -11,6 +11,7 @@
 #include <filesystem>
 #include <fstream>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -1161,6 +1162,93 @@ extern "C" tnlm_status tnlm_batch_timing_enable(tnlm_batch *b, int32_t enable) {
 extern "C" tnlm_status tnlm_batch_timing_read(tnlm_batch *b, double *ms, int32_t *launches) {
     if (!b) return fail(TNLM_E_INVALID_ARG, "null batch");
     return timing_read(&b->e, ms, launches);
+}
+
+// ---------------------------------------------------------------------------
+// Regulariser sweep of one slice without a context and without allocation.
+// The kernel's tables (slice descriptor, work-item prefix, XCD ranges) live in
+// a library-owned device array; its address on each GPU is looked up once,
+// with that GPU current, on the first call there.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = 1024;
+constexpr size_t kScratchPre = 256, kScratchXb = 512;   // byte offsets of the prefix and XCD tables
+static_assert(sizeof(SliceDesc) <= kScratchPre && kScratchPre + 2 * sizeof(int) <= kScratchXb &&
+                  kScratchXb + 9 * sizeof(int) <= kNoAllocScratchBytes,
+              "the tables of one slice fit the scratch array");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+struct NoAllocTables {
+    SliceDesc d;
+    int pre[2];
+    int xb[9];
+};
+
+// One lane writes the tables; the regulariser launched after it on the same
+// stream reads them.
+__global__ void k_write_noalloc_tables(unsigned char *dst, NoAllocTables t) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    *reinterpret_cast<SliceDesc *>(dst) = t.d;
+    int *pre = reinterpret_cast<int *>(dst + kScratchPre);
+    pre[0] = t.pre[0];
+    pre[1] = t.pre[1];
+    int *xb = reinterpret_cast<int *>(dst + kScratchXb);
+    for (int k = 0; k < 9; ++k) xb[k] = t.xb[k];
+}
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static tnlm_status scratch_of_current_device(unsigned char **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(TNLM_E_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(TNLM_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    return TNLM_OK;
+}
+
+extern "C" tnlm_status tnlm_regularize_noalloc(int32_t n_phases, int32_t L, int32_t patch, int32_t window, float h,
+                                               float mu_hat, const float *d_guide, const float *d_value,
+                                               const float *d_g, float *d_out, int32_t clamp, void *stream) {
+    if (!d_guide || !d_value || !d_g || !d_out) return fail(TNLM_E_INVALID_ARG, "null device pointer");
+    if (d_out == d_guide || d_out == d_value || d_out == d_g)
+        return fail(TNLM_E_INVALID_ARG, "d_out must not alias an input");
+    if (n_phases < 1 || L < 1 || L > 4096 || (long long)n_phases * L * L > (1LL << 31))
+        return fail(TNLM_E_SHAPE, "need N >= 1, 1 <= L <= 4096 and N L^2 <= 2^31");
+    if (!reg_supported(patch, window)) return fail(TNLM_E_INVALID_ARG, "patch must be odd in [3,9], window odd in [3,21]");
+    if (window > L) return fail(TNLM_E_SHAPE, "window larger than the image");
+    if (!(h > 0.0f) || !std::isfinite(h)) return fail(TNLM_E_INVALID_ARG, "h must be > 0");
+    if (!(mu_hat >= 0.0f) || !std::isfinite(mu_hat)) return fail(TNLM_E_INVALID_ARG, "mu_hat must be >= 0");
+    constexpr int kRowsPerLane = 4;   // any tile height gives the same bits
+    NoAllocTables t{};
+    t.d.N = n_phases;
+    t.d.L = L;
+    const long long items = (long long)reg_blocks(t.d, patch, kRowsPerLane);
+    if (items < 1 || items > (1LL << 30)) return fail(TNLM_E_SHAPE, "too many regulariser tiles");
+    t.d.nrb = (int)items;
+    t.pre[0] = 0;
+    t.pre[1] = (int)items;
+    for (int x = 0; x <= 8; ++x) t.xb[x] = (int)(items * x / 8);
+    unsigned char *ptr = nullptr;
+    const tnlm_status ss = scratch_of_current_device(&ptr);
+    if (ss != TNLM_OK) return ss;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    k_write_noalloc_tables<<<1, 64, 0, st>>>(ptr, t);
+    Batch bt;
+    bt.ns = 1;
+    bt.sl = reinterpret_cast<const SliceDesc *>(ptr);
+    Stage sg{reinterpret_cast<const int *>(ptr + kScratchPre), reinterpret_cast<const int *>(ptr + kScratchXb),
+             (int)items, std::max(1, std::min((int)items, kCUs * 4)), 0};
+    if (sg.grid >= 8) sg.grid -= sg.grid % 8;
+    RegParams rp{patch, window, h, mu_hat};
+    launch_regularize(bt, sg, rp, kRowsPerLane, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr, nullptr, st);
+    return last_launch();
 }
 
 extern "C" const char *tnlm_status_string(tnlm_status s) {

@@ -78,3 +78,20 @@ def test_nonfinite_view_angle_rejected():
     ang[1, 2] = np.nan
     ctx = C.c_void_p()
     assert nat.lib.tnlm_recon_init(C.byref(ctx), C.byref(G), C.byref(P), None) == -5
+
+
+def test_noalloc_regulariser_rejects_bad_arguments():
+    """tnlm_regularize_noalloc checks its arguments before any HIP call."""
+    from paper_1009_1351_amd import _native as nat
+    f = nat.lib.tnlm_regularize_noalloc
+    a, b, c, d = C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_void_p(64)
+    assert f(2, 16, 3, 5, 0.01, 0.5, None, b, c, d, 1, None) == -1          # null input
+    assert f(2, 16, 3, 5, 0.01, 0.5, a, b, c, a, 1, None) == -1             # output aliases an input
+    assert f(2, 5000, 3, 5, 0.01, 0.5, a, b, c, d, 1, None) == -2           # L beyond 4096
+    assert f(0, 16, 3, 5, 0.01, 0.5, a, b, c, d, 1, None) == -2             # no phase
+    assert f(200, 4096, 3, 5, 0.01, 0.5, a, b, c, d, 1, None) == -2         # N L^2 beyond 2^31
+    assert f(2, 16, 4, 5, 0.01, 0.5, a, b, c, d, 1, None) == -1             # even patch
+    assert f(2, 4, 3, 5, 0.01, 0.5, a, b, c, d, 1, None) == -2              # window beyond the image
+    assert f(2, 16, 3, 5, 0.0, 0.5, a, b, c, d, 1, None) == -1              # h = 0
+    assert f(2, 16, 3, 5, 0.01, -1.0, a, b, c, d, 1, None) == -1            # mu_hat < 0
+    assert b"4096" in nat.lib.tnlm_last_error() or len(nat.lib.tnlm_last_error()) > 0
