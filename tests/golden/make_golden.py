@@ -14,6 +14,8 @@ Names and what each file holds (float32 images, float64 histories):
                   256^2 with 56 views; bins 1.5 L), 50 outer iterations
   c4s0            slice 0 of the 512^2 precision workload (120 views x 720
                   bins), 50 outer iterations
+  c1tol           the 64^2 workload solved from the FBP of all phases until
+                  the relative update falls below 1e-4 (cap 400 iterations)
 
 Both sides see the same float32-rounded inputs and parameters: y, w and the
 regulariser input are rounded to float32 and widened, h and mu_hat likewise.
@@ -46,7 +48,9 @@ TRAJECTORIES = {
     "c3s6": ("C3", 6),
     "c3s34": ("C3", 34),
     "c4s0": ("C4", 0),
+    "c1tol": ("C1", 0),
 }
+TOLERANCES = {"c1tol": (1e-4, 400)}   # (relative-update tolerance, iteration cap) of solves run to a tolerance
 
 
 def f32(a):
@@ -87,7 +91,9 @@ def make_trajectory(name):
     config, s = TRAJECTORIES[name]
     case = synth.make_case(config, slice_index=s)
     y, w = f32(case.y), f32(case.w)
-    prm = oracle.case_params(case, h=float(np.float32(case.h)), mu_hat=float(np.float32(case.mu_hat)))
+    tol, cap = TOLERANCES.get(name, (case.tol, case.max_outer))
+    prm = oracle.case_params(case, h=float(np.float32(case.h)), mu_hat=float(np.float32(case.mu_hat)), tol=tol,
+                             max_outer=cap)
     t0 = time.perf_counter()
     f, k, rel, hist = oracle.solve(oracle.Geometry(case.geom), prm, y, w)
     dt = time.perf_counter() - t0
@@ -121,4 +127,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["sweep256", "c2c", "c2b", "c3s6", "c3s34", "c2a", "c4s0"])
+    main(sys.argv[1:] or ["sweep256", "c2c", "c2b", "c3s6", "c3s34", "c2a", "c4s0", "c1tol"])
