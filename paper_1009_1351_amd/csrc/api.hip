@@ -84,6 +84,7 @@ struct Engine {
     double *relpart = nullptr;
     double *cost_part = nullptr;   // [1024] partials of the data-term reduction
     int *flags = nullptr;   // [4][ns]: done, counter, nonfinite, spare
+    int *queue = nullptr;   // [16]: work-item counters of the persistent stages (cleared by each launch)
     float *hist = nullptr;  // [ns][max_outer]
     float *Y = nullptr, *Wt = nullptr, *F = nullptr;   // batch copies of caller arrays
     size_t nimg = 0, nsino = 0;
@@ -456,6 +457,12 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8, kbp)) != TNLM_OK) return st;
     E.st_fp.cu_runs = 1;
     E.st_bp.cu_runs = 1;
+    // one set of work-item counters serves the persistent stages: their
+    // launches are ordered on the engine's stream, and each launch leaves the
+    // counters cleared
+    HIP_TRY(E.alloc(&E.queue, 16));
+    HIP_TRY(hipMemset(E.queue, 0, 16 * sizeof(int)));
+    E.st_fp.queue = E.st_bp.queue = E.st_reg.queue = E.queue;
     if ((st = make_stage(E, E.st_vec, cvec, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_reg, creg, kCUs * 4)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_ffilt, cff, kCUs * 8)) != TNLM_OK) return st;

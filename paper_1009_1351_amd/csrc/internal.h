@@ -40,6 +40,7 @@ struct Stage {
     int total;        // pre[ns]
     int grid;         // persistent grid size
     int cu_runs = 0;  // 1: blocks sharing a CU take consecutive work items
+    int *queue = nullptr;   // device [9] (nullable): per-XCD item counters and a finished-block count
 };
 
 struct Batch {
@@ -115,6 +116,48 @@ __device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stri
     first = load_const(st.xb, x) + k;
     stride = per_x;
     count = load_const(st.xb, x + 1);
+}
+
+// Work items of a stage for one block. With a queue, the blocks of XCD x
+// take the items [xb[x], xb[x+1]) one at a time, in the order they ask, from
+// a counter: the items an XCD works on at once stay consecutive for the whole
+// launch (with a fixed grid-stride order, blocks drift apart over the many
+// items each takes, until the XCD works on images from several phases and
+// slices at once and its L2 no longer holds them). The last block to finish
+// clears the counters for the next launch. Results do not depend on which
+// block takes an item. Without a queue, the fixed order of xcd_range.
+// Every thread of the block must call work_next and work_end.
+struct WorkIter {
+    int cur, stride, end, x;
+};
+
+__device__ __forceinline__ WorkIter work_begin(const Stage &st) {
+    WorkIter it;
+    xcd_range(st, it.cur, it.stride, it.end);
+    it.x = (int)blockIdx.x % 8;
+    return it;
+}
+
+__device__ __forceinline__ bool work_next(const Stage &st, WorkIter &it, int &gb, int *sh_item) {
+    if (st.queue && gridDim.x >= 8) {
+        if (threadIdx.x == 0) *sh_item = load_const(st.xb, it.x) + atomicAdd(st.queue + it.x, 1);
+        __syncthreads();
+        gb = *sh_item;
+        __syncthreads();   // read by every thread before the next item's grab
+        return gb < it.end;
+    }
+    gb = it.cur;
+    it.cur += it.stride;
+    return gb < it.end;
+}
+
+__device__ __forceinline__ void work_end(const Stage &st) {
+    if (!st.queue || gridDim.x < 8 || threadIdx.x != 0) return;
+    __threadfence();
+    if (atomicAdd(st.queue + 8, 1) == (int)gridDim.x - 1) {   // every block has finished taking items
+        for (int k = 0; k < 9; ++k) st.queue[k] = 0;
+        __threadfence();
+    }
 }
 
 // ---- projector (proj.hip)

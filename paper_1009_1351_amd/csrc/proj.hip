@@ -217,9 +217,10 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
                                                     const float *__restrict__ sw, float *__restrict__ out,
                                                     float *__restrict__ out2, double *__restrict__ partials) {
     __shared__ double sh[kBlock];
-    int first, stride, count;
-    xcd_range(st, first, stride, count);
-    for (int gb = first; gb < count; gb += stride) {
+    __shared__ int sh_item;
+    WorkIter it = work_begin(st);
+    int gb;
+    while (work_next(st, it, gb, &sh_item)) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
         const SliceDesc sd = load_const(bt.sl, s);
@@ -268,6 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
             if (threadIdx.x == 0) partials[sd.qp0 + (long long)i * sd.npp + v * nbx + bx] = tot;
         }
     }
+    work_end(st);
 }
 
 void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *fT, const float *y,
@@ -363,10 +365,11 @@ int bp_blocks(const SliceDesc &s) {
 __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, const float *__restrict__ q,
                                                         float *__restrict__ fout, double *__restrict__ partials) {
     __shared__ double sh[kBlock];
-    int first, stride, count;
-    xcd_range(st, first, stride, count);
+    __shared__ int sh_item;
+    WorkIter it = work_begin(st);
+    int gb;
     const int tx = threadIdx.x % kBpLanes, ty = threadIdx.x / kBpLanes;
-    for (int gb = first; gb < count; gb += stride) {
+    while (work_next(st, it, gb, &sh_item)) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
         const SliceDesc sd = load_const(bt.sl, s);
@@ -463,6 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
             if (threadIdx.x == 0) partials[sd.gp0 + (long long)i * sd.nbp + tcy * nt + tcx] = tot;
         }
     }
+    work_end(st);
 }
 
 void launch_backproject(const Batch &b, const Stage &st, const float *q, float *f, double *partials,

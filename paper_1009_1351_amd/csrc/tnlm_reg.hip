@@ -124,9 +124,10 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
     const int R = a.R;
     const int TCW = 32 + 2 * R, TRH = TH + 2 * S + 2 * R, TS = TCW * TRH;
     const bool same = a.value == a.guide;
-    int first, stride, count;
-    xcd_range(st, first, stride, count);
-    for (int gb = first; gb < count; gb += stride) {
+    __shared__ int sh_item;
+    WorkIter it = work_begin(st);
+    int gb;
+    while (work_next(st, it, gb, &sh_item)) {
     const int sidx = find_slice(st.pre, bt.ns, gb);
     if (bt.skip && bt.skip[sidx]) continue;
     const SliceDesc sd = bt.sl[sidx];
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
         }
     }
     }   // work items
+    work_end(st);
 }
 
 // Regularisation term of Eq. 1 for one slice: the sum over phases i, both

@@ -99,9 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg_mfma(Batch bt, Stage st, Re
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n16 = lane & 15, kg = lane >> 4;
 
-    int first, stride, count;
-    xcd_range(st, first, stride, count);
-    for (int gb = first; gb < count; gb += stride) {
+    __shared__ int sh_item;
+    WorkIter it = work_begin(st);
+    int gb;
+    while (work_next(st, it, gb, &sh_item)) {
         const int sidx = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[sidx]) continue;
         const SliceDesc sd = bt.sl[sidx];
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg_mfma(Batch bt, Stage st, Re
             }
         }
     }
+    work_end(st);
 }
 
 int reg_mfma_blocks(const SliceDesc &s) {
