@@ -69,7 +69,8 @@ struct Engine {
     int4 *vo = nullptr;
     float *hfilt = nullptr, *cw = nullptr;
     Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{}, st_tr{};
-    float *fT = nullptr;   // transposed copy of the image a projection reads
+    float *fP = nullptr, *fTP = nullptr;   // padded row-major and transposed copies a projection reads
+    size_t npimg = 0;                       // elements of each padded copy
     const float *fixed_guide = nullptr;   // caller's weight guide for every iteration (null: g^(k))
     struct StageSpec {
         Stage *st;
@@ -368,7 +369,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     std::vector<double> crossings(ns, 0.0);
     E.angles.resize(ns);
     E.sl.resize(ns);
-    long long ray = 0, view = 0, img = 0, sino = 0;
+    long long ray = 0, view = 0, img = 0, sino = 0, pimg = 0;
     int gp = 0, qp = 0, rpp = 0, phase = 0;
     for (int s = 0; s < ns; ++s) {
         const tnlm_geometry &g = geoms[s];
@@ -386,6 +387,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         d.ray0 = ray;
         d.view0 = view;
         d.img0 = img;
+        d.pimg0 = pimg;
         d.sino0 = sino;
         d.hf0 = (int)hf.size();
         d.cw0 = (int)cw.size();
@@ -406,9 +408,11 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         ray += (long long)d.N * d.V * d.B;
         view += (long long)d.N * d.V;
         img += (long long)d.N * d.L * d.L;
+        pimg += (long long)d.N * d.L * (d.L + 2);
         sino += (long long)d.N * d.V * d.B;
     }
     E.nimg = (size_t)img;
+    E.npimg = (size_t)pimg;
     E.nsino = (size_t)sino;
     HIP_TRY(E.alloc(&E.d_sl, ns));
     HIP_TRY(hipMemcpy(E.d_sl, E.sl.data(), ns * sizeof(SliceDesc), hipMemcpyHostToDevice));
@@ -469,7 +473,11 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     if ((st = make_stage(E, E.st_fbp_all, cfa, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_fbp_ph, cfph, kCUs * 8)) != TNLM_OK) return st;
     if ((st = make_stage(E, E.st_tr, ctr, kCUs * 8)) != TNLM_OK) return st;
-    HIP_TRY(E.alloc(&E.fT, E.nimg));
+    HIP_TRY(E.alloc(&E.fP, E.npimg));
+    HIP_TRY(E.alloc(&E.fTP, E.npimg));
+    // the zero columns of the padded copies; kernels write only the interior
+    HIP_TRY(hipMemset(E.fP, 0, E.npimg * sizeof(float)));
+    HIP_TRY(hipMemset(E.fTP, 0, E.npimg * sizeof(float)));
 
     CglsBufs &b = E.cb;
     HIP_TRY(E.alloc(&b.u, E.nimg));
@@ -509,22 +517,22 @@ static void enqueue_data_step(Engine *E, const Batch &bt, const float *y, const 
     hipStream_t st = E->cur;
     const int M1 = E->prm.m1_cgls;
     if (M1 == 0) {
-        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, f, E->fT, st));
+        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, f, E->fP, E->fTP, st));
         TIMED(E, K_PROJECT,
-              launch_project(bt, E->st_fp, PROJ_PLAIN, f, E->fT, nullptr, nullptr, b.q, nullptr, nullptr, st));
+              launch_project(bt, E->st_fp, PROJ_PLAIN, E->fP, E->fTP, nullptr, nullptr, b.q, nullptr, nullptr, st));
         TIMED(E, K_VECTOR, launch_weighted_resid(bt, E->st_vec, b.q, y, w, E->Q, st));
         TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, E->Q, b.t, nullptr, st));
         TIMED(E, K_VECTOR, launch_gradient_step(bt, E->st_vec, f, b.t, 1.0f / E->prm.beta, b.u, st));
         return;
     }
     TIMED(E, K_VECTOR, launch_copy_skip(bt, E->st_vec, true, f, b.u, st));
-    TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.u, E->fT, st));
-    TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_RESID, b.u, E->fT, y, b.sw, b.r, b.rw, nullptr, st));
+    TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.u, E->fP, E->fTP, st));
+    TIMED(E, K_PROJECT, launch_project(bt, E->st_fp, PROJ_RESID, E->fP, E->fTP, y, b.sw, b.r, b.rw, nullptr, st));
     TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.s, b.gpart[0], st));
     for (int m = 0; m < M1; ++m) {
-        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.s, E->fT, st));
+        TIMED(E, K_VECTOR, launch_transpose(bt, E->st_tr, b.s, E->fP, E->fTP, st));
         TIMED(E, K_PROJECT,
-              launch_project(bt, E->st_fp, PROJ_SCALED, b.s, E->fT, nullptr, b.sw, b.q, nullptr, b.qpart, st));
+              launch_project(bt, E->st_fp, PROJ_SCALED, E->fP, E->fTP, nullptr, b.sw, b.q, nullptr, b.qpart, st));
         TIMED(E, K_VECTOR, launch_cgls_update(bt, E->st_vec, b, m, m & 1, st));
         if (m + 1 < M1) {
             TIMED(E, K_BACKPROJECT, launch_backproject(bt, E->st_bp, b.rw, b.t, b.gpart[(m + 1) & 1], st));
@@ -919,8 +927,8 @@ extern "C" tnlm_status tnlm_project(tnlm_ctx *ctx, const float *d_f, float *d_q)
     if (!d_f || !d_q) return fail(TNLM_E_INVALID_ARG, "null device pointer");
     Engine *E = &ctx->e;
     E->cur = E->stream;
-    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fT, E->stream));
-    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, E->fT, nullptr, nullptr, d_q, nullptr,
+    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fP, E->fTP, E->stream));
+    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, E->fP, E->fTP, nullptr, nullptr, d_q, nullptr,
                                        nullptr, E->stream));
     return last_launch();
 }
@@ -983,8 +991,8 @@ extern "C" tnlm_status tnlm_data_cost(tnlm_ctx *ctx, const float *d_y, const flo
     if (!d_y || !d_w || !d_f || !out) return fail(TNLM_E_INVALID_ARG, "null pointer");
     Engine *E = &ctx->e;
     E->cur = E->stream;
-    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fT, E->stream));
-    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, d_f, E->fT, nullptr, nullptr, E->cb.q,
+    TIMED(E, K_VECTOR, launch_transpose(E->batch, E->st_tr, d_f, E->fP, E->fTP, E->stream));
+    TIMED(E, K_PROJECT, launch_project(E->batch, E->st_fp, PROJ_PLAIN, E->fP, E->fTP, nullptr, nullptr, E->cb.q,
                                        nullptr, nullptr, E->stream));
     const int nb = launch_wsq_sum(E->cb.q, d_y, d_w, E->nsino, E->cost_part, E->stream);
     std::vector<double> part(nb);

@@ -27,6 +27,7 @@ struct SliceDesc {
     long long view0; // first view in the view table ([N][V])
     long long img0;  // first element in image-shaped arrays ([N][L][L])
     long long sino0; // first element in sinogram-shaped arrays ([N][V][B])
+    long long pimg0; // first element in the projector's padded image copies ([N][L][L + 2])
     int gp0, qp0, rp0;   // first partial slot in gpart / qpart / relpart
     int nbp, npp, nrb;   // partial slots per phase (transpose, projector) and per slice (regulariser)
     int hf0, cw0;        // first entry of this slice's FBP filter taps (2B-1) and cosine weights (B)
@@ -165,8 +166,11 @@ enum ProjMode { PROJ_PLAIN = 0, PROJ_RESID = 1, PROJ_SCALED = 2 };
 int proj_blocks(const SliceDesc &s);
 int bp_blocks(const SliceDesc &s);
 int tr_blocks(const SliceDesc &s);
-// fT: the same image stack transposed per phase (launch_transpose)
-void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fT, hipStream_t strm);
+// fP, fTP: the image stack copied row-major and transposed per phase, each
+// row padded with a zero column on either side ([N][L][L + 2] per slice at
+// pimg0; the owner of the buffers clears the zero columns once)
+void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fP, float *fTP, hipStream_t strm);
+// f, fT: the padded copies written by launch_transpose
 void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *fT, const float *y,
                     const float *sw, float *out, float *out2, double *partials, hipStream_t strm);
 void launch_backproject(const Batch &b, const Stage &st, const float *q, float *f, double *partials,

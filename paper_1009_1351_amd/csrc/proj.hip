@@ -13,7 +13,8 @@
 //
 // Forward: one lane per ray, lanes = consecutive bins of one view, walking
 // the image row by row in step (adjacent rays read neighbouring pixels of one
-// row, writes are coalesced). Transpose: one lane
+// row, writes are coalesced); rows in which every ray of a wave is inside the
+// image take an unmasked loop. Transpose: one lane
 // per pixel, a deterministic gather over views and the pixel's candidate
 // bins (no floating-point atomics). Both are persistent over the batch's
 // ragged slice table.
@@ -24,20 +25,33 @@ namespace tnlm {
 
 __device__ __forceinline__ float plane_t(int k, float A, float B) { return fmaf((float)k, A, B); }
 
-constexpr int kRaysPerBlock = kBlock;
+// Rays per lane (adjacent bins; the walk is written for any count). One:
+// two rays per lane give each pass twice the arithmetic to cover the
+// latency of its reads, but spread a wave's reads over twice the cache
+// lines and raise the registers to 76 (6 waves per SIMD); measured slower.
+constexpr int kProjRays = 1;
+constexpr int kRaysPerBlock = kBlock * kProjRays;
 
 int proj_blocks(const SliceDesc &s) { return s.N * s.V * ((s.B + kRaysPerBlock - 1) / kRaysPerBlock); }
 
-// Image reads of the walk go through a buffer resource spanning one phase
-// image: an offset outside it reads 0 without a memory access (the walk
-// prefetches the cell after the current one, which lies outside the image
-// once the ray leaves it).
+// The walk reads zero-padded copies of the image stack: each row of L pixels
+// is stored with one zero column on either side (row stride L + 2, pixel
+// (r, c) at r (L + 2) + c + 1), so the cell just past a side of the image
+// reads 0. Reads go through a buffer resource spanning one padded phase
+// image: an offset outside it reads 0 without a memory access.
+__device__ __forceinline__ int padded_stride(int L) { return L + 2; }
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float *fi, int L) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(fi), (short)0, L * L * 4, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(fi), (short)0, L * padded_stride(L) * 4, 0x00020000);
 }
 
 __device__ __forceinline__ float image_at(__amdgpu_buffer_rsrc_t img, int byte_off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, byte_off, 0, 0));
+}
+
+// Cells c and c + dc of a row (byte offsets off and off + ox): two reads.
+__device__ __forceinline__ float2 image_two(__amdgpu_buffer_rsrc_t img, int off, int ox) {
+    return make_float2(image_at(img, off), image_at(img, off + ox));
 }
 
 __device__ __forceinline__ float cell_clip(float xl, float xh, float yl, float yh) {
@@ -45,27 +59,29 @@ __device__ __forceinline__ float cell_clip(float xl, float xh, float yl, float y
 }
 
 // Offset that the image's buffer resource turns into a read of 0 without a
-// memory access (beyond the L x L image for every L the engine accepts).
+// memory access (beyond the padded L x (L + 2) image for every L the engine
+// accepts, also after the steps a lane that takes no part adds to it).
 constexpr int kNoCell = 0x40000000;
 
-// Row-synchronous walk of one wave's rays over one phase image (L x L). The
-// plane tables A (x planes in .x/.y, y planes in .z/.w) and ray points O come
-// in the wave's frame, in which every ray of the wave crosses about one
-// column per row or fewer. Pass p visits image row p counted along the rays'
-// row direction for all lanes at once, so the lanes of a wave read
-// neighbouring cells of one row (two per lane: the current column and the
-// next) rather than drifting apart by their different numbers of column
-// crossings. The length of each cell is the clip of the transpose kernel and
-// cells are added in the order the ray meets them (a ray that reaches the next
-// column exactly at the row's upper plane enters it with length 0 first), so
-// the sum is bitwise that of a walk crossing one grid line at a time. The wave
-// runs from the first entry row to the last exit row of its rays; a lane that
-// leaves through a side stops adding there, and a ray crossing two columns in
-// one row takes the rare inner loop.
-// Must be called by all lanes of the wave; lanes with valid = false add nothing.
-__device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool valid,
-                                           __amdgpu_buffer_rsrc_t img, int L, float X0, float invD) {
-    int pin = L, pout = -1, c = 0, dc = 1, dr = 1, hc = 1, hr = 1;
+// State of one ray's walk between passes. Column c holds the ray at the
+// start of a pass (its upper x plane txh = T_x(fkx) lies beyond the pass's
+// lower y plane tyl); rowoff is the byte offset of column -1 of the pass's
+// row in the padded image; v1, v2 are the cells (r, c) and (r, c + dc) read
+// ahead for the pass. pin, pout and pside are the passes of the ray's entry
+// row, of its exit row (with margin) and of the row in which it leaves
+// through the side it runs towards (L if it leaves through the far row edge).
+struct Walk {
+    int c, dc, rowoff, ox, oy, pin, pout, pside;
+    float fkx, fky, dcf, drf, txh, tyl, tin, acc;
+    float v1, v2;             // cells c and c + dc of the pass's row
+    bool hit, dead;
+};
+
+// Entry and exit of one ray (plane tables A: x planes in .x/.y, y planes in
+// .z/.w, and ray points O, both in the wave's frame).
+__device__ __forceinline__ void walk_setup(Walk &w, const float4 A, const float4 O, bool valid, int L, float X0,
+                                           float invD) {
+    int pin = L, pout = -1, pside = L, c = 0, dc = 1, dr = 1, hc = 1, hr = 1;
     float tin = 0.0f;
     bool hit = false;
     if (valid) {
@@ -97,69 +113,274 @@ __device__ __forceinline__ float walk_rows(const float4 A, const float4 O, bool 
             int re = (int)floorf((fmaf(tout, O.w, O.y) - X0) * invD);
             re = min(max(re, 0), L - 1);
             pout = min((dr > 0 ? re : L - 1 - re) + 2, L - 1);
+            // pass in which the walk meets the side plane it runs towards (the
+            // first pass whose upper y plane is not below that plane's T, the
+            // comparison the walk makes), or L if it leaves through the far row
+            // edge first: estimated from the point on that plane, then settled
+            // on the plane values
+            const float tse = plane_t(dc > 0 ? L : 0, A.x, A.y);
+            int rs = (int)floorf((fmaf(tse, O.w, O.y) - X0) * invD);
+            rs = min(max(rs, 0), L - 1);
+            int ps = max(dr > 0 ? rs : L - 1 - rs, pin);
+            auto ty_up = [&](int p) { return plane_t((dr > 0 ? p : L - 1 - p) + hr, A.z, A.w); };
+            while (ps > pin && tse <= ty_up(ps - 1)) --ps;
+            while (ps < L && !(tse <= ty_up(ps))) ++ps;
+            pside = ps;
         }
     }
-    int p0 = pin, p1 = pout;   // first and last pass of the wave
+    w.c = c;
+    w.dc = dc;
+    w.ox = 4 * dc;
+    w.dcf = (float)dc;
+    w.drf = (float)dr;
+    w.fkx = (float)(c + hc);
+    w.txh = plane_t(c + hc, A.x, A.y);
+    w.tin = tin;
+    w.acc = 0.0f;
+    w.hit = hit;
+    w.dead = !hit;
+    w.pin = pin;
+    w.pout = pout;
+    w.pside = pside;
+    (void)hr;
+}
+
+// Row-dependent part of the state at the wave's first pass p0.
+__device__ __forceinline__ void walk_start(Walk &w, const float4 A, int L, int p0) {
+    const int dr = w.drf > 0.0f ? 1 : -1, hr = dr > 0 ? 1 : 0;
+    const int r0 = dr > 0 ? p0 : L - 1 - p0;
+    const int LP = padded_stride(L);
+    w.oy = 4 * dr * LP;
+    w.rowoff = 4 * r0 * LP;
+    w.fky = (float)(r0 + hr);
+    w.tyl = plane_t(r0 + 1 - hr, A.z, A.w);
+}
+
+__device__ __forceinline__ void walk_load(Walk &w, __amdgpu_buffer_rsrc_t img, bool live) {
+    const int o1 = live ? w.rowoff + 4 * w.c + 4 : kNoCell;
+    const float2 v = image_two(img, o1, w.ox);
+    w.v1 = v.x;
+    w.v2 = v.y;
+}
+
+// One pass of one ray with the masks that rows before its entry row and
+// after its side exit need. At the start of a pass a live ray's column c
+// holds it and the column's upper x plane lies beyond the row's lower y
+// plane (txh > tyl), so the clip of (r, c) is non-negative and that of
+// (r, c + dc) has max(txh, tyl) = txh: both are the transpose kernel's clips
+// without its clamp. The lower x plane of column c is at most tyl in every
+// row but the entry row, where it is tin or at most tin = tyl, so
+// max(x_lo, tyl) = max(tin, tyl) throughout. A ray that is not live reads 0.
+__device__ __forceinline__ void masked_pass(Walk &w, int p, const float4 A, __amdgpu_buffer_rsrc_t img, int L) {
+    const bool live = !w.dead && p >= w.pin;
+    const float tyh = fmaf(w.fky, A.z, A.w);
+    const float txn = fmaf(w.fkx + w.dcf, A.x, A.y);
+    const float l1 = fminf(w.txh, tyh) - fmaxf(w.tin, w.tyl);
+    const float l2 = fminf(txn, tyh) - w.txh;
+    const bool cross = live && w.txh <= tyh;   // reaches the next column in this row
+    const bool in2 = (unsigned)(w.c + w.dc) < (unsigned)L;
+    const bool take2 = cross && in2;
+    w.acc = fmaf(l1, w.v1, w.acc);
+    w.acc = fmaf(take2 ? l2 : 0.0f, w.v2, w.acc);
+    w.dead = w.dead || (cross && !in2);   // left the image through a side
+    w.c = take2 ? w.c + w.dc : w.c;
+    w.fkx = take2 ? w.fkx + w.dcf : w.fkx;
+    w.txh = take2 ? txn : w.txh;
+    while (take2 && w.txh <= tyh) {   // a further column in the same row
+        if ((unsigned)(w.c + w.dc) >= (unsigned)L) {
+            w.dead = true;
+            break;
+        }
+        const float tx3 = fmaf(w.fkx + w.dcf, A.x, A.y);
+        w.acc = fmaf(cell_clip(w.txh, tx3, w.tyl, tyh), image_at(img, w.rowoff + 4 * (w.c + w.dc) + 4), w.acc);
+        w.c += w.dc;
+        w.fkx += w.dcf;
+        w.txh = tx3;
+    }
+    w.tyl = tyh;
+    w.fky += w.drf;
+    w.rowoff += w.oy;
+    walk_load(w, img, !w.dead && p + 1 >= w.pin);   // next row's cells, in flight during the next pass
+}
+
+// Passes [pa, pb) of both rays with masks.
+__device__ __forceinline__ void walk_masked(Walk (&w)[kProjRays], int pa, int pb, const float4 (&A)[kProjRays],
+                                            __amdgpu_buffer_rsrc_t img, int L) {
+    if (pa >= pb) return;
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) walk_load(w[j], img, !w[j].dead && pa >= w[j].pin);
+    for (int p = pa; p < pb; ++p) {
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) masked_pass(w[j], p, A[j], img, L);
+    }
+}
+
+// Unmasked stretch of one ray: the carried state between its passes.
+struct Steady {
+    float lo, edge;
+    float va1, va2, vb1, vb2;   // cells of alternate passes (no load's destination is copied: a copy waits)
+    int o1, ox, oy, oxy;
+};
+
+__device__ __forceinline__ void steady_begin(Steady &s, Walk &w, __amdgpu_buffer_rsrc_t img, int L) {
+    s.lo = fmaxf(w.tin, w.tyl);
+    // the column ahead lies past the side once dc * fkx >= dc * (plane index
+    // of that side): the current column is the last one or already outside
+    s.edge = w.dcf * (w.dc > 0 ? (float)L : 0.0f);
+    s.ox = w.hit ? w.ox : 0;
+    s.oy = w.hit ? w.oy : 0;
+    s.oxy = s.ox + s.oy;
+    if (!w.hit) w.txh = INFINITY;   // never crosses a column: sp = tyh, l2 = 0, and it reads 0
+    s.o1 = w.hit ? w.rowoff + 4 * w.c + 4 : kNoCell;   // cell c of the pass
+    const float2 v = image_two(img, s.o1, s.ox);
+    s.va1 = v.x;
+    s.va2 = v.y;
+    s.vb1 = s.vb2 = 0.0f;
+}
+
+// One unmasked pass of one ray. The arithmetic of each entry is that of
+// masked_pass for a live ray:
+//   * lo = max(tin, tyl) at the stretch's first pass and tyl after it (tin <
+//     tyl once the entry row is behind);
+//   * the length in column c + dc is min(txn, tyh) - min(txh, tyh): the
+//     masked pass's min(txn, tyh) - txh when the ray reaches that column in
+//     this row (txh <= tyh), and exactly 0 when it does not (txn >= txh >
+//     tyh), so no mask is needed;
+//   * a ray leaving through a side in the stretch's last pass reads the zero
+//     padding as its cell (r, c + dc) and adds 0.
+// The next pass's cells (cv1, cv2 are this pass's; nv1, nv2 receive the
+// next's) are requested as soon as their column is known: it follows from
+// this pass's crossing test alone unless the ray crosses two columns in this
+// row (then they are requested again). The column is tracked through the
+// read offset o1 and the plane index fkx only.
+__device__ __forceinline__ void steady_pass(Steady &s, Walk &w, const float4 A, __amdgpu_buffer_rsrc_t img,
+                                            const float &cv1, const float &cv2, float &nv1, float &nv2) {
+    const float tyh = fmaf(w.fky, A.z, A.w);
+    const bool cross = w.txh <= tyh;
+    int o1n = s.o1 + (cross ? s.oxy : s.oy);   // next row; next column too when the ray reaches it
+    {
+        const float2 nv = image_two(img, o1n, s.ox);
+        nv1 = nv.x;
+        nv2 = nv.y;
+    }
+    const float fkn = w.fkx + w.dcf;
+    const float txn = fmaf(fkn, A.x, A.y);
+    const float sp = fminf(w.txh, tyh);
+    const float l1 = sp - s.lo;
+    const float l2 = fminf(txn, tyh) - sp;
+    w.acc = fmaf(l1, cv1, w.acc);
+    w.acc = fmaf(l2, cv2, w.acc);
+    w.fkx = cross ? fkn : w.fkx;
+    w.txh = cross ? txn : w.txh;
+    if (cross && w.txh <= tyh) {   // a further column in the same row (rare)
+        int oc = o1n - s.oy;   // the column entered, in this pass's row
+        while (w.txh <= tyh) {
+            if (w.dcf * w.fkx >= s.edge) {   // the next column is past the side: step onto it and stop
+                w.fkx += w.dcf;             // (this is the ray's side-exit pass, the stretch's last)
+                break;
+            }
+            const float tx3 = fmaf(w.fkx + w.dcf, A.x, A.y);
+            w.acc = fmaf(cell_clip(w.txh, tx3, s.lo, tyh), image_at(img, oc + s.ox), w.acc);
+            oc += s.ox;
+            w.fkx += w.dcf;
+            w.txh = tx3;
+        }
+        o1n = oc + s.oy;
+        const float2 rv = image_two(img, o1n, s.ox);
+        nv1 = rv.x;
+        nv2 = rv.y;
+    }
+    s.lo = tyh;
+    w.fky += w.drf;
+    s.o1 = o1n;
+}
+
+// Passes [pa, pb] in which every ray of the wave that meets the image is
+// inside it: at or after its entry row and at or before the row in which it
+// leaves through a side. Rays that miss the image read at kNoCell with
+// ox = oy = 0 and add 0.
+__device__ __forceinline__ void walk_steady(Walk (&w)[kProjRays], int pa, int pb, const float4 (&A)[kProjRays],
+                                            __amdgpu_buffer_rsrc_t img, int L) {
+    if (pa > pb) return;
+    Steady s[kProjRays];
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) steady_begin(s[j], w[j], img, L);
+    int p = pa;
+    for (; p < pb; p += 2) {
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) steady_pass(s[j], w[j], A[j], img, s[j].va1, s[j].va2, s[j].vb1, s[j].vb2);
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) steady_pass(s[j], w[j], A[j], img, s[j].vb1, s[j].vb2, s[j].va1, s[j].va2);
+    }
+    if (p == pb) {
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) steady_pass(s[j], w[j], A[j], img, s[j].va1, s[j].va2, s[j].vb1, s[j].vb2);
+    }
+    // back to the masked walk's state: column from the plane index; a ray
+    // whose column is past a side left the image in the stretch's last pass
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) {
+        w[j].tyl = s[j].lo;
+        if (w[j].hit) {
+            w[j].rowoff += (pb - pa + 1) * w[j].oy;
+            w[j].c = (int)w[j].fkx - (w[j].dc > 0 ? 1 : 0);
+            if ((unsigned)w[j].c >= (unsigned)L) w[j].dead = true;
+        }
+    }
+}
+
+// Row-synchronous walk of one wave's rays over one phase image (L x L,
+// padded). The plane tables and ray points come in the wave's frame, in
+// which every ray of the wave crosses about one column per row or fewer.
+// Pass p visits image row p counted along the rays' row direction for all
+// rays at once, so the lanes of a wave read neighbouring cells of one row
+// (two per ray: the current column and the next) rather than drifting apart
+// by their different numbers of column crossings. The length of each cell is
+// the clip of the transpose kernel and cells are added in the order the ray
+// meets them (a ray that reaches the next column exactly at the row's upper
+// plane enters it with length 0 first), so the sum is bitwise that of a walk
+// crossing one grid line at a time. The wave runs from the first entry row
+// to the last exit row of its rays, in three stretches: masked passes up to
+// the last entry row of the wave, unmasked passes while every ray is inside
+// the image, masked passes after the first side exit; a ray crossing two
+// columns in one row takes the rare inner loop.
+// Must be called by all lanes of the wave; rays with valid = false add nothing.
+__device__ __forceinline__ void walk_rows(const float4 (&A)[kProjRays], const float4 (&O)[kProjRays],
+                                          const bool (&valid)[kProjRays], __amdgpu_buffer_rsrc_t img, int L,
+                                          float X0, float invD, float (&acc)[kProjRays]) {
+    Walk w[kProjRays];
+    int p0 = L, p1 = -1, pa = 0, pb = L;
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) {
+        walk_setup(w[j], A[j], O[j], valid[j], L, X0, invD);
+        p0 = min(p0, w[j].pin);
+        p1 = max(p1, w[j].pout);
+        if (w[j].hit) {
+            pa = max(pa, w[j].pin);
+            pb = min(pb, w[j].pside);
+        }
+    }
     for (int m = 32; m > 0; m >>= 1) {
         p0 = min(p0, __shfl_xor(p0, m, 64));
         p1 = max(p1, __shfl_xor(p1, m, 64));
+        pa = max(pa, __shfl_xor(pa, m, 64));
+        pb = min(pb, __shfl_xor(pb, m, 64));
     }
     p0 = wave_uniform(p0);
     p1 = wave_uniform(p1);
-    const int r0 = dr > 0 ? p0 : L - 1 - p0;
-    const float dcf = (float)dc, drf = (float)dr;
-    const int ox = 4 * dc, oy = 4 * dr * L;
-    float fkx = (float)(c + hc), fky = (float)(r0 + hr);
-    float txh = plane_t(c + hc, A.x, A.y);
-    float tyl = plane_t(r0 + 1 - hr, A.z, A.w);
-    int rowoff = 4 * r0 * L;
-    bool dead = !hit;
-    bool live = hit && p0 >= pin;
-    int o1 = live ? rowoff + 4 * c : kNoCell;
-    float v1 = image_at(img, o1), v2 = image_at(img, o1 + ox);
-    float acc = 0.0f;
-    for (int p = p0; p <= p1; ++p) {
-        // At the start of a row a live lane's column c holds its ray and the
-        // column's upper x plane lies beyond the row's lower y plane
-        // (txh > tyl), so the clip of (r, c) is non-negative and that of
-        // (r, c + dc) has max(txh, tyl) = txh: both are the transpose
-        // kernel's clips without its clamp. The lower x plane of column c
-        // is at most tyl in every row but the entry row, where it is tin or
-        // at most tin = tyl, so max(x_lo, tyl) = max(tin, tyl) throughout.
-        // Lanes that are not live read 0.
-        const float tyh = fmaf(fky, A.z, A.w);
-        const float txn = fmaf(fkx + dcf, A.x, A.y);
-        const float l1 = fminf(txh, tyh) - fmaxf(tin, tyl);
-        const float l2 = fminf(txn, tyh) - txh;
-        const bool cross = live && txh <= tyh;   // reaches the next column in this row
-        const bool in2 = (unsigned)(c + dc) < (unsigned)L;
-        const bool take2 = cross && in2;
-        acc = fmaf(l1, v1, acc);
-        acc = fmaf(take2 ? l2 : 0.0f, v2, acc);
-        dead = dead || (cross && !in2);   // left the image through a side
-        c = take2 ? c + dc : c;
-        fkx = take2 ? fkx + dcf : fkx;
-        txh = take2 ? txn : txh;
-        while (take2 && txh <= tyh) {   // a further column in the same row
-            if ((unsigned)(c + dc) >= (unsigned)L) {
-                dead = true;
-                break;
-            }
-            const float tx3 = fmaf(fkx + dcf, A.x, A.y);
-            acc = fmaf(cell_clip(txh, tx3, tyl, tyh), image_at(img, rowoff + 4 * (c + dc)), acc);
-            c += dc;
-            fkx += dcf;
-            txh = tx3;
-        }
-        tyl = tyh;
-        fky += drf;
-        rowoff += oy;
-        live = !dead && p + 1 >= pin;
-        o1 = live ? rowoff + 4 * c : kNoCell;
-        v1 = image_at(img, o1);   // next row's cells, in flight during the next pass's plane arithmetic
-        v2 = image_at(img, o1 + ox);
+    pa = max(wave_uniform(pa), p0);   // first pass of the unmasked stretch
+    pb = min(wave_uniform(pb), p1);   // its last pass
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) walk_start(w[j], A[j], L, p0);
+    if (pa <= pb) {
+        walk_masked(w, p0, pa, A, img, L);
+        walk_steady(w, pa, pb, A, img, L);
+        walk_masked(w, pb + 1, p1 + 1, A, img, L);
+    } else {
+        walk_masked(w, p0, p1 + 1, A, img, L);
     }
-    return acc;
+#pragma unroll
+    for (int j = 0; j < kProjRays; ++j) acc[j] = w[j].acc;
 }
 
 // Image stacks are row-major, (r, c) at r L + c. A projector wave walks rows
@@ -176,8 +397,12 @@ int tr_blocks(const SliceDesc &s) {
     return s.N * t * t;
 }
 
+// One pass over the image stack writes both padded copies the projector
+// reads: row-major and transposed, each row with a zero column on either side
+// (the zero columns are cleared once when the buffers are allocated and never
+// written).
 __global__ __launch_bounds__(kBlock) void k_transpose(Batch bt, Stage st, const float *__restrict__ f,
-                                                      float *__restrict__ fT) {
+                                                      float *__restrict__ fP, float *__restrict__ fTP) {
     __shared__ float tile[kTr][kTr + 1];
     int first, stride, count;
     xcd_range(st, first, stride, count);
@@ -191,24 +416,30 @@ __global__ __launch_bounds__(kBlock) void k_transpose(Batch bt, Stage st, const 
         const int bx = lb % t;
         lb /= t;
         const int by = lb % t, i = lb / t;
+        const int LP = L + 2;
         const float *__restrict__ src = f + sd.img0 + (long long)i * L * L;
-        float *__restrict__ dst = fT + sd.img0 + (long long)i * L * L;
+        float *__restrict__ dst = fP + sd.pimg0 + (long long)i * L * LP;
+        float *__restrict__ dstT = fTP + sd.pimg0 + (long long)i * L * LP;
         for (int k = 0; k < kTr; k += kBlock / kTr) {
             const int r = by * kTr + ty + k, c = bx * kTr + tx;
-            if (r < L && c < L) tile[ty + k][tx] = src[r * L + c];
+            if (r < L && c < L) {
+                const float v = src[r * L + c];
+                tile[ty + k][tx] = v;
+                dst[r * LP + c + 1] = v;
+            }
         }
         __syncthreads();
         for (int k = 0; k < kTr; k += kBlock / kTr) {
             const int c = bx * kTr + ty + k, r = by * kTr + tx;
-            if (r < L && c < L) dst[c * L + r] = tile[tx][ty + k];
+            if (r < L && c < L) dstT[c * LP + r + 1] = tile[tx][ty + k];
         }
         __syncthreads();
     }
 }
 
-void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fT, hipStream_t strm) {
+void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fP, float *fTP, hipStream_t strm) {
     if (st.total == 0) return;
-    k_transpose<<<st.grid, kBlock, 0, strm>>>(b, st, f, fT);
+    k_transpose<<<st.grid, kBlock, 0, strm>>>(b, st, f, fP, fTP);
 }
 
 template <int MODE>
@@ -229,47 +460,60 @@ __global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const fl
         const int bx = lb % nbx;
         lb /= nbx;
         const int v = lb % sd.V, i = lb / sd.V;
-        const int b = bx * kRaysPerBlock + threadIdx.x;
-        const long long ray = ((long long)i * sd.V + v) * sd.B + b;   // within the slice
+        const int b0 = bx * kRaysPerBlock + kProjRays * threadIdx.x;   // the lane's rays: b0, b0 + 1
+        const long long ray0 = ((long long)i * sd.V + v) * sd.B + b0;   // within the slice
         const int L = sd.L;
-        const bool valid = b < sd.B;
-        float4 A = make_float4(1.0f, 0.0f, 1.0f, 0.0f), O = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-        if (valid) {
-            A = bt.rt0[sd.ray0 + ray];
-            O = bt.rt1[sd.ray0 + ray];
+        float4 A[kProjRays], O[kProjRays];
+        bool valid[kProjRays];
+        int nval = 0, nxmaj = 0;
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) {
+            valid[j] = b0 + j < sd.B;
+            A[j] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
+            O[j] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+            if (valid[j]) {
+                A[j] = bt.rt0[sd.ray0 + ray0 + j];
+                O[j] = bt.rt1[sd.ray0 + ray0 + j];
+            }
+            nval += __popcll(__ballot(valid[j]));
+            nxmaj += __popcll(__ballot(valid[j] && fabsf(A[j].x) < fabsf(A[j].z)));
         }
         // the wave walks the transposed image, axes exchanged, when most of
         // its rays cross columns faster than rows
-        const bool xmaj = valid && fabsf(A.x) < fabsf(A.z);
-        const bool tr = wave_uniform(2 * __popcll(__ballot(xmaj)) > __popcll(__ballot(valid)));
+        const bool tr = wave_uniform(2 * nxmaj > nval ? 1 : 0) != 0;
         if (tr) {
-            A = make_float4(A.z, A.w, A.x, A.y);
-            O = make_float4(O.y, O.x, O.w, O.z);
+#pragma unroll
+            for (int j = 0; j < kProjRays; ++j) {
+                A[j] = make_float4(A[j].z, A[j].w, A[j].x, A[j].y);
+                O[j] = make_float4(O[j].y, O[j].x, O[j].w, O[j].z);
+            }
         }
-        const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.img0 + (long long)i * L * L, L);
-        const float acc = walk_rows(A, O, valid, img, L, sd.X0, 1.0f / sd.D);
+        const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.pimg0 + (long long)i * L * (L + 2), L);
+        float acc[kProjRays];
+        walk_rows(A, O, valid, img, L, sd.X0, 1.0f / sd.D, acc);
         double part = 0.0;
-        if (b < sd.B) {
-            const long long e = sd.sino0 + ray;
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) {
+            if (!valid[j]) continue;
+            const long long e = sd.sino0 + ray0 + j;
             if (MODE == PROJ_PLAIN) {
-                out[e] = acc;
+                out[e] = acc[j];
             } else if (MODE == PROJ_RESID) {   // r = sw (y - P u), rw = sw r
                 const float w = sw[e];
-                const float res = w * (y[e] - acc);
+                const float res = w * (y[e] - acc[j]);
                 out[e] = res;
                 out2[e] = w * res;
             } else {                           // q = sw P s, partial ||q||^2
-                const float qv = sw[e] * acc;
+                const float qv = sw[e] * acc[j];
                 out[e] = qv;
-                part = (double)qv * (double)qv;
+                part += (double)qv * (double)qv;
             }
         }
         if (MODE == PROJ_SCALED) {
             const double tot = block_sum_256(part, sh);
             if (threadIdx.x == 0) partials[sd.qp0 + (long long)i * sd.npp + v * nbx + bx] = tot;
         }
-    }
-    work_end(st);
+    }    work_end(st);
 }
 
 void launch_project(const Batch &b, const Stage &st, int mode, const float *f, const float *fT, const float *y,
@@ -465,8 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, cons
             const double tot = block_sum_256(sq, sh);
             if (threadIdx.x == 0) partials[sd.gp0 + (long long)i * sd.nbp + tcy * nt + tcx] = tot;
         }
-    }
-    work_end(st);
+    }    work_end(st);
 }
 
 void launch_backproject(const Batch &b, const Stage &st, const float *q, float *f, double *partials,
@@ -474,5 +717,7 @@ void launch_backproject(const Batch &b, const Stage &st, const float *q, float *
     if (st.total == 0) return;
     k_backproject<<<st.grid, kBlock, 0, strm>>>(b, st, q, f, partials);
 }
+
+
 
 }  // namespace tnlm
