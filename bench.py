@@ -468,24 +468,56 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
 
 
 def summarize_counters(out_md, title, command, dirs):
-    """A counter table (per kernel kind: mean per dispatch of each counter)
-    from one or more rocprofv3 --pmc runs, written to profiles/<out_md>."""
+    """A counter table from one or more rocprofv3 --pmc runs, written to
+    profiles/<out_md>: per kernel kind, the mean per dispatch of each counter
+    over the dispatches of full size (launches on the whole batch; set-up
+    launches of the tile autotuner on one slice are left out), and derived
+    figures:
+      time       = GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz
+      VALU issue = SQ_INSTS_VALU / (256 CUs x time cycles): a CU issues at
+                   most one wave-wide VALU instruction per cycle
+      lanes      = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU)
+      MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (256 CUs x time cycles)
+      LDS conflict cycles per LDS instruction = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS"""
     import csv
     from collections import defaultdict
-    vals = defaultdict(lambda: defaultdict(list))
+    rows = []
     for d in dirs:
-        for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
-            k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
-            if k:
-                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        rows += list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
+    grid = defaultdict(int)
+    for r in rows:
+        k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
+        if k:
+            grid[k] = max(grid[k], int(r["Grid_Size"]))
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in rows:
+        k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
+        if k and (k == "conv" or int(r["Grid_Size"]) * 2 > grid[k]):
+            vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     names = sorted({c for k in vals for c in vals[k]})
     out = [f"# {title}", "", "Commands (repository root):", ""] + ["    " + c for c in command.split(" ;; ")] + [
-        "", "Mean per dispatch:", "", "| kind | dispatches | " + " | ".join(names) + " |",
-        "|---|---|" + "---|" * len(names)]
+        "", "Mean per dispatch (full-size dispatches):", "",
+        "| kind | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
     for k in sorted(vals):
         n = max(len(v) for v in vals[k].values())
         cells = [f"{np.mean(vals[k][c]):.4g}" if vals[k].get(c) else "-" for c in names]
         out.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    out += ["", "Derived (formulas in bench.py summarize_counters):", "",
+            "| kind | time ms | VALU issue | lanes active | MFMA busy | LDS conflict cycles / LDS instr |",
+            "|---|---|---|---|---|---|"]
+    for k in sorted(vals):
+        m = {c: float(np.mean(v)) for c, v in vals[k].items()}
+        gui = m.get("GRBM_GUI_ACTIVE")
+        cyc = gui / 8.0 if gui else None
+
+        def frac(a, den):
+            return f"{a / den:.3f}" if a is not None and den else "-"
+        out.append(f"| {k} | {cyc / 2.4e6:.3f} | " if cyc else f"| {k} | - | ")
+        out[-1] += " | ".join([
+            frac(m.get("SQ_INSTS_VALU"), 256 * cyc if cyc else None),
+            frac(m.get("SQ_THREAD_CYCLES_VALU"), 64 * m["SQ_ACTIVE_INST_VALU"] if m.get("SQ_ACTIVE_INST_VALU") else None),
+            frac(m.get("SQ_VALU_MFMA_BUSY_CYCLES"), 256 * cyc if cyc else None),
+            frac(m.get("SQ_LDS_BANK_CONFLICT"), m.get("SQ_INSTS_LDS"))]) + " |"
     out.append("")
     open(os.path.join(ROOT, "profiles", out_md), "w").write("\n".join(out))
 
