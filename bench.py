@@ -474,8 +474,10 @@ def summarize_counters(out_md, title, command, dirs):
     launches of the tile autotuner on one slice are left out), and derived
     figures:
       time       = GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz
-      VALU issue = SQ_INSTS_VALU / (256 CUs x time cycles): a CU issues at
-                   most one wave-wide VALU instruction per cycle
+      VALU issue = SQ_INSTS_VALU / (256 CUs x time cycles): wave-wide VALU
+                   instructions per CU per clock; the ceiling depends on the
+                   mix (streams of independent FP32 FMAs reach 0.90, compare /
+                   select / add 1.33, integer add / shift / xor 1.59)
       lanes      = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU)
       MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (256 CUs x time cycles)
       LDS conflict cycles per LDS instruction = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS"""
@@ -484,19 +486,23 @@ def summarize_counters(out_md, title, command, dirs):
     rows = []
     for d in dirs:
         rows += list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
+    conv = {"k_conv_fwd": "conv_fwd", "k_conv_wgrad": "conv_wgrad"}
+
+    def kind(name):
+        return kind_of(name) or next((v for c, v in conv.items() if c in name), None)
     grid = defaultdict(int)
     for r in rows:
-        k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
+        k = kind(r["Kernel_Name"])
         if k:
             grid[k] = max(grid[k], int(r["Grid_Size"]))
     vals = defaultdict(lambda: defaultdict(list))
     for r in rows:
-        k = kind_of(r["Kernel_Name"]) or ("conv" if "cnn::" in r["Kernel_Name"] else None)
-        if k and (k == "conv" or int(r["Grid_Size"]) * 2 > grid[k]):
+        k = kind(r["Kernel_Name"])
+        if k and (k.startswith("conv") or int(r["Grid_Size"]) * 2 > grid[k]):
             vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     names = sorted({c for k in vals for c in vals[k]})
     out = [f"# {title}", "", "Commands (repository root):", ""] + ["    " + c for c in command.split(" ;; ")] + [
-        "", "Mean per dispatch (full-size dispatches):", "",
+        "", "Mean per dispatch (full-size dispatches; all dispatches of the network kernels):", "",
         "| kind | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
     for k in sorted(vals):
         n = max(len(v) for v in vals[k].values())
