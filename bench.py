@@ -367,7 +367,8 @@ def quality_leg(torch, dev, iters=50):
 
 # ------------------------------------------------------- profile summaries
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
-           "k_tnlm_reg_mfma<": "regularize_bf16", "k_transpose(": "transpose"}
+           "k_tnlm_reg_mfma<": "regularize_bf16", "k_tnlm_sym<": "regularize", "k_tnlm_sym_finish(": "regularize_finish",
+           "k_transpose(": "transpose"}
 
 
 def kind_of(name):
@@ -559,8 +560,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-timing-pass", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--learned-slices", type=int, default=C5_EVAL_SLICES)
-    ap.add_argument("--ssd-mode", default="fp32", choices=("fp32", "bf16_mfma"),
-                    help="patch distances of the timed batch (the workload is fp32)")
+    ap.add_argument("--ssd-mode", default="fp32_sym", choices=("fp32", "bf16_mfma", "fp32_sym"),
+                    help="regulariser of the timed batch: fp32_sym (default) forms each unordered phase pair's "
+                         "weights once for both directions, fp32 each phase's two neighbours on its own, bf16_mfma "
+                         "the distances on the matrix cores")
     ap.add_argument("--cnn", action="store_true", help="run only the network leg (for profiling)")
     ap.add_argument("--gen-workers", type=int, default=0, help="input generation processes (0: one per core, <= 16)")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 256 MiB device copy (counter scale)")
@@ -634,12 +637,16 @@ def main():
     out = {
         "metric": "phase-pixel*iters/s", "value": value, "unit": "phase-pixel*iters/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if a.ssd_mode == "fp32" else "f32+bf16",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16" if a.ssd_mode == "bf16_mfma" else "f32",
         "data": "synthetic",
         "config": {"workload": f"mixed batch: {len(cases)} slices x 10 phases, L from {{128,256,384,512}}, 40-360 "
                                "views, 1.5 L bins, I0 1e4-1e6; patch 7, window 15, M1 3, M2 1; "
                                f"{a.iters} outer iterations from the FBP of all phases, one batched solve per step "
-                               "(one outer iteration replayed as a HIP graph)",
+                               "(one outer iteration replayed as a HIP graph); regulariser "
+                               + {"fp32_sym": "fp32 with the weights of each unordered phase pair formed once for "
+                                              "both directions",
+                                  "fp32": "fp32, each phase's two neighbours on their own",
+                                  "bf16_mfma": "with bf16 MFMA patch distances"}[a.ssd_mode],
                    "slices_per_step": len(cases), "wall_s_per_slice": dt / slices,
                    "phase_pixel_iters_per_step": units // max(a.steps, 1), "parallelism": "single GPU"},
     }

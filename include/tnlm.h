@@ -54,7 +54,22 @@ typedef enum {
 } tnlm_status;
 
 enum { TNLM_INIT_FBP_ALL = 0, TNLM_INIT_USER = 1 };
-enum { TNLM_SSD_FP32 = 0, TNLM_SSD_BF16_MFMA = 1 };
+/* How the regulariser forms the patch distances and weights of Eq. 8:
+ *   TNLM_SSD_FP32            FP32 box sums, per-pixel running-minimum shift;
+ *   TNLM_SSD_BF16_MFMA       cross terms on the BF16 matrix cores (patch 3, 5, 7;
+ *                            window <= 15), compensated hi/lo split;
+ *   TNLM_SSD_FP32_SYMMETRIC  the symmetric reuse of §2.3: each unordered pair of
+ *                            neighbouring phases once, one distance and one
+ *                            unshifted exponential per pair serving both
+ *                            directions; a pixel whose weight sum underflows
+ *                            (below 2^-60) is recomputed exactly. Same result
+ *                            as TNLM_SSD_FP32 up to rounding; needs one extra
+ *                            image of forward sums and per-tile partial sums
+ *                            (about 6 floats per image element). Window 21,
+ *                            and window 19 with patch 3, need more than
+ *                            64 KiB of LDS per block and are rejected with
+ *                            TNLM_E_INVALID_ARG. */
+enum { TNLM_SSD_FP32 = 0, TNLM_SSD_BF16_MFMA = 1, TNLM_SSD_FP32_SYMMETRIC = 2 };
 
 typedef struct {
     int32_t n_phases;        /* N >= 1, phases on a ring (§2.1)               */
@@ -80,7 +95,7 @@ typedef struct {
     int32_t max_outer;       /* >= 1 outer iterations (cap)                    */
     float tol_rel_update;    /* stop when ||F^k - F^k-1|| / ||F^k|| < tol; 0 = run max_outer */
     int32_t init;            /* TNLM_INIT_FBP_ALL or TNLM_INIT_USER            */
-    int32_t ssd_mode;        /* TNLM_SSD_FP32 or TNLM_SSD_BF16_MFMA            */
+    int32_t ssd_mode;        /* TNLM_SSD_FP32, _BF16_MFMA or _FP32_SYMMETRIC   */
 } tnlm_params;
 
 typedef struct tnlm_ctx tnlm_ctx;

@@ -21,7 +21,8 @@ _lib = C.CDLL(LIB_PATH)
 
 TNLM_OK, TNLM_W_NOT_CONVERGED = 0, 1
 INIT_FBP_ALL, INIT_USER = 0, 1
-SSD_FP32, SSD_BF16_MFMA = 0, 1
+SSD_FP32, SSD_BF16_MFMA, SSD_FP32_SYMMETRIC = 0, 1, 2
+SSD_MODES = {"fp32": SSD_FP32, "bf16_mfma": SSD_BF16_MFMA, "fp32_sym": SSD_FP32_SYMMETRIC}
 
 
 class Geometry(C.Structure):

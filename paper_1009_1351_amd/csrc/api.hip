@@ -83,6 +83,8 @@ struct Engine {
     CglsBufs cb{};
     float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
+    float2 *symfwd = nullptr;   // symmetric-reuse regulariser: forward sums per image element
+    float *sympart = nullptr;   // and reverse partial sums per work item
     double *cost_part = nullptr;   // [1024] partials of the data-term reduction
     int *flags = nullptr;   // [4][ns]: done, counter, nonfinite, spare
     int *queue = nullptr;   // [16]: work-item counters of the persistent stages (cleared by each launch)
@@ -213,8 +215,10 @@ static tnlm_status validate_params(const tnlm_params *p, int minL) {
     if (p->max_outer < 1 || p->max_outer > 100000) return fail(TNLM_E_INVALID_ARG, "max_outer must be >= 1");
     if (!(p->tol_rel_update >= 0)) return fail(TNLM_E_INVALID_ARG, "tol_rel_update must be >= 0");
     if (p->init != TNLM_INIT_FBP_ALL && p->init != TNLM_INIT_USER) return fail(TNLM_E_INVALID_ARG, "bad init");
-    if (p->ssd_mode != TNLM_SSD_FP32 && p->ssd_mode != TNLM_SSD_BF16_MFMA)
+    if (p->ssd_mode != TNLM_SSD_FP32 && p->ssd_mode != TNLM_SSD_BF16_MFMA && p->ssd_mode != TNLM_SSD_FP32_SYMMETRIC)
         return fail(TNLM_E_INVALID_ARG, "bad ssd_mode");
+    if (p->ssd_mode == TNLM_SSD_FP32_SYMMETRIC && !reg_sym_supported(p->patch, p->window))
+        return fail(TNLM_E_INVALID_ARG, "ssd_mode FP32_SYMMETRIC: patch and window need more LDS than a block has");
     if (p->ssd_mode == TNLM_SSD_BF16_MFMA && !reg_mfma_supported(p->patch, p->window))
         return fail(TNLM_E_INVALID_ARG, "ssd_mode BF16_MFMA supports patch 3, 5, 7 and window <= 15");
     return TNLM_OK;
@@ -357,7 +361,9 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     // this (patch, window, L) class, else tuned at the end of the set-up
     const char *env_rpl = std::getenv("TNLM_ROWS_PER_LANE");
     const int cached_rpl = env_rpl ? (std::atoi(env_rpl) == 4 ? 4 : 8) : autotuned_rows_per_lane(*params, geoms[0].L);
-    E.rows_per_lane = cached_rpl ? cached_rpl : 8;
+    E.rows_per_lane = params->ssd_mode == TNLM_SSD_FP32_SYMMETRIC ? reg_sym_rows_per_lane()
+                      : cached_rpl                                  ? cached_rpl
+                                                                    : 8;
     const bool tune_now = cached_rpl == 0 && params->ssd_mode == TNLM_SSD_FP32;
     const char *env_graph = std::getenv("TNLM_NO_GRAPH");
     E.use_graph = !(env_graph && env_graph[0] == '1');
@@ -498,6 +504,10 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         HIP_TRY(E.alloc(&E.ub, E.nimg));
     }
     HIP_TRY(E.alloc(&E.relpart, 2 * (size_t)rpp));
+    if (params->ssd_mode == TNLM_SSD_FP32_SYMMETRIC) {
+        HIP_TRY(E.alloc(&E.symfwd, E.nimg));
+        HIP_TRY(E.alloc(&E.sympart, (size_t)rpp * reg_sym_part_floats(params->patch, params->window)));
+    }
     HIP_TRY(E.alloc(&E.flags, 4 * (size_t)ns));
     HIP_TRY(E.alloc(&E.cost_part, 1024));
     HIP_TRY(E.alloc(&E.hist, (size_t)ns * params->max_outer));
@@ -554,6 +564,11 @@ static void enqueue_regularize(Engine *E, const Batch &bt, float *f, bool record
             TIMED(E, K_REGULARIZE,
                   launch_regularize_mfma(bt, E->st_reg, E->rp, guide, val, g, dst, last ? 1 : 0,
                                          last && record ? E->relpart : nullptr, E->nonfinite(), E->cur));
+        else if (E->prm.ssd_mode == TNLM_SSD_FP32_SYMMETRIC)
+            TIMED(E, K_REGULARIZE,
+                  launch_regularize_sym(bt, E->st_reg, E->rp, guide, val, g, dst, last ? 1 : 0,
+                                        last && record ? E->relpart : nullptr, E->nonfinite(), E->symfwd,
+                                        E->sympart, E->cur));
         else
             TIMED(E, K_REGULARIZE,
                   launch_regularize(bt, E->st_reg, E->rp, E->rows_per_lane, guide, val, g, dst, last ? 1 : 0,
@@ -978,6 +993,10 @@ extern "C" tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, cons
         TIMED(E, K_REGULARIZE,
               launch_regularize_mfma(E->batch, E->st_reg, E->rp, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr,
                                      nullptr, E->stream));
+    else if (E->prm.ssd_mode == TNLM_SSD_FP32_SYMMETRIC)
+        TIMED(E, K_REGULARIZE,
+              launch_regularize_sym(E->batch, E->st_reg, E->rp, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr,
+                                    nullptr, E->symfwd, E->sympart, E->stream));
     else
         TIMED(E, K_REGULARIZE,
               launch_regularize(E->batch, E->st_reg, E->rp, E->rows_per_lane, d_guide, d_value, d_g, d_out,

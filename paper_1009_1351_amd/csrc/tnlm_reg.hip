@@ -423,4 +423,455 @@ void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int 
     else launch_by<8>(b, st, p.patch / 2, a, lds, strm);
 }
 
+
+// ---------------------------------------------------------------------------
+// Symmetric reuse (§2.3): the distance between the patch of x in phase i and
+// the patch of y in phase i+1 is also the distance between the patch of y in
+// phase i+1 and the patch of x in phase i, so the unnormalised weight
+// exp(-D/h^2) of Eq. 8 serves both directions. One block takes one tile T of
+// one unordered pair (i, i+1) and every offset of the window:
+//   * forward (phase i, pixel x in T, neighbour i+1): sums over the window of
+//     w * value_{i+1}(y) and of w, in registers as in the kernel above;
+//   * reverse (phase i+1, pixel y = x + delta, neighbour i): the same w times
+//     value_i(x), added into an LDS region covering T grown by the window
+//     radius; the pixels of that region near its rim also receive terms from
+//     the neighbouring tiles, so the block writes the region's sums out and a
+//     second kernel adds the (at most four) tiles' sums of each pixel.
+// One exponential and one distance per pair of directions, against two of
+// each when every phase computes both neighbours itself. The weights are not
+// shifted by the per-pixel minimum, which no single pass can know for the
+// reverse direction: exp2(D * nk) <= 1 cannot overflow, and where a pixel's
+// weight sum falls below 2^-60 (a best match more than ~40 h^2 away, where
+// terms below 2^-126 would be lost) the second kernel recomputes that
+// direction of that pixel exactly, with the running minimum.
+//
+// Waves split the window's offsets in four row-major quarters; each wave owns
+// its own reverse region (no two lanes of one wave instruction meet the same
+// y, and no two waves share a region), so every sum is taken in a fixed
+// order. LDS float atomics cost about eight times a read and a write here,
+// so the sums are plain read-add-writes. A region holds sum w v and sum w in
+// planes of alternate columns (the 16 lanes of a band touch 16 consecutive
+// words) with a row stride that puts bands 0, 1 (and 2, 3) of a wave on
+// opposite halves of the 32 banks.
+
+struct SymArgs {
+    int R, rwh;          // window radius; row stride of one column-parity plane of a reverse region
+    float nk;            // -log2(e) / h^2
+    const float *guide, *value;
+    float2 *fwd;         // [image elements]: forward (sum w v, sum w) of phase i toward i+1
+    float *part;         // [work items][RH][RW][2]: reverse (sum w v, sum w) of each tile's region
+};
+
+template <int S, int kBY>
+__global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs a) {
+#pragma clang fp contract(off)
+    extern __shared__ float lds[];
+    constexpr int TW = 32 - 2 * S, TH = 4 * kBY, NR = kBY + 2 * S;
+    const int R = a.R, W = 2 * R + 1, WW = W * W;
+    const int TCW = 32 + 2 * R, TRH = TH + 2 * S + 2 * R, TS = TCW * TRH;
+    const int RW = TW + 2 * R, RH = TH + 2 * R;
+    const int rwh = a.rwh, pl = RH * rwh;   // pairs in one parity plane
+    const bool same = a.value == a.guide;
+    float *tg = lds, *tv = same ? lds : lds + TS;
+    float *rev = lds + (same ? 1 : 2) * TS;
+    __shared__ int sh_item;
+    WorkIter it = work_begin(st);
+    int gb;
+    while (work_next(st, it, gb, &sh_item)) {
+        const int sidx = find_slice(st.pre, bt.ns, gb);
+        if (bt.skip && bt.skip[sidx]) continue;
+        const SliceDesc sd = bt.sl[sidx];
+        const int L = sd.L, N = sd.N;
+        const int ntx = (L + TW - 1) / TW, nty = (L + TH - 1) / TH;
+        const int lb = gb - st.pre[sidx];
+        const int tile_local = lb % (ntx * nty);
+        const int i = lb / (ntx * nty), j = (i + 1) % N;
+        const int x0 = (tile_local % ntx) * TW, y0 = (tile_local / ntx) * TH;
+        const size_t plane = (size_t)L * L;
+        const float *guide = a.guide + sd.img0, *value = a.value + sd.img0;
+
+        __syncthreads();   // LDS reuse across work items
+        const int col0 = x0 - S - R, row0 = y0 - S - R;
+        for (int e = threadIdx.x; e < TS; e += kBlock) {
+            const int tr = e / TCW, tc = e - tr * TCW;
+            const int gr = min(max(row0 + tr, 0), L - 1), gc = min(max(col0 + tc, 0), L - 1);
+            const size_t off = (size_t)gr * L + gc;
+            tg[e] = guide[j * plane + off];
+            if (!same) tv[e] = value[j * plane + off];
+        }
+        for (int e = threadIdx.x; e < 16 * pl; e += kBlock) rev[e] = 0.0f;
+
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int l16 = lane & 15, band = lane >> 4;
+        const int xa = x0 - S + 2 * l16;
+        const int zbase = y0 + band * kBY - S;
+        const int yb = y0 + band * kBY;
+        float gia[NR], gib[NR], via[kBY], vib[kBY];
+        {
+            const float *gi = guide + (size_t)i * plane, *vi = value + (size_t)i * plane;
+            const int ca = min(max(xa, 0), L - 1), cb = min(max(xa + 1, 0), L - 1);
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const int zr = min(max(zbase + k, 0), L - 1);
+                gia[k] = gi[(size_t)zr * L + ca];
+                gib[k] = gi[(size_t)zr * L + cb];
+            }
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                const int zr = min(yb + o, L - 1);
+                via[o] = vi[(size_t)zr * L + ca];
+                vib[o] = vi[(size_t)zr * L + cb];
+            }
+        }
+        const bool va = lane_valid_a<S>(l16) && xa >= x0 && xa < x0 + TW && xa < L;
+        const bool vb = lane_valid_b<S>(l16) && xa + 1 >= x0 && xa + 1 < x0 + TW && xa + 1 < L;
+        float numa[kBY], dena[kBY], numb[kBY], denb[kBY];
+#pragma unroll
+        for (int o = 0; o < kBY; ++o) numa[o] = dena[o] = numb[o] = denb[o] = 0.0f;
+        __syncthreads();
+
+        const int ta = 2 * l16 + R, trb = band * kBY + R;
+        const float nk = a.nk;
+        float *rw = rev + wave * 4 * pl;
+        const int k0 = wave * WW / 4, k1 = (wave + 1) * WW / 4;
+        int dy = k0 / W - R, dx = k0 % W - R;
+        for (int k = k0; k < k1; ++k) {
+            // the neighbour's values at y (in bounds for every lane): read
+            // first, so the distance arithmetic hides their latency
+            const float *vp = tv + (band * kBY + S + R + dy) * TCW + ta + dx;
+            float vya[kBY], vyb[kBY];
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                vya[o] = vp[o * TCW];
+                vyb[o] = vp[o * TCW + 1];
+            }
+            float ha[NR], hb[NR];
+            const float *rowp = tg + (trb + dy) * TCW + ta + dx;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const float da = gia[q] - rowp[q * TCW];
+                const float db = gib[q] - rowp[q * TCW + 1];
+                const float eb = db * db;
+                hsum<S>(da * da, eb, fmaf(da, da, eb), ha[q], hb[q]);
+            }
+            const bool ca = va && (unsigned)(xa + dx) < (unsigned)L;
+            const bool cb = vb && (unsigned)(xa + 1 + dx) < (unsigned)L;
+            // reverse region column of y = x + delta for column a (the b column
+            // is the next one, in the other parity plane); rows from band start
+            const int cy = 2 * l16 - S + dx + R;
+            const int par = cy & 1;
+            float *ra = rw + par * pl + (cy >> 1) + (band * kBY + dy + R) * rwh;
+            float *rb = rw + (par ^ 1) * pl + ((cy + 1) >> 1) + (band * kBY + dy + R) * rwh;
+            float p2a[NR - 1], p2b[NR - 1];
+#pragma unroll
+            for (int q = 0; q + 1 < NR; ++q) {
+                p2a[q] = ha[q] + ha[q + 1];
+                p2b[q] = hb[q] + hb[q + 1];
+            }
+            float wa[kBY], wva[kBY], wb[kBY], wvb[kBY];   // reverse terms, 0 for pairs outside the image
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                float Da = ha[o + 2 * S], Db = hb[o + 2 * S];
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    Da += p2a[o + 2 * q];
+                    Db += p2b[o + 2 * q];
+                }
+                // both ends inside the image: y's row here, x's row too (rows of
+                // the last tile row past the image must not reach y's sums)
+                const bool rv = (unsigned)(yb + o + dy) < (unsigned)L && yb + o < L;
+                wa[o] = wva[o] = wb[o] = wvb[o] = 0.0f;
+                if (rv && ca) {
+                    const float w = __builtin_amdgcn_exp2f(Da * nk);
+                    numa[o] = fmaf(w, vya[o], numa[o]);
+                    dena[o] += w;
+                    wa[o] = w;
+                    wva[o] = w * via[o];
+                }
+                if (rv && cb) {
+                    const float w = __builtin_amdgcn_exp2f(Db * nk);
+                    numb[o] = fmaf(w, vyb[o], numb[o]);
+                    denb[o] += w;
+                    wb[o] = w;
+                    wvb[o] = w * vib[o];
+                }
+            }
+            // reverse sums: every row of a valid column lies inside the region
+            // (adding 0 leaves a sum unchanged), so all reads go out before the
+            // writes
+            if (va) {
+                float n[kBY], d[kBY];
+#pragma unroll
+                for (int o = 0; o < kBY; ++o) {
+                    n[o] = ra[o * rwh];
+                    d[o] = ra[o * rwh + 2 * pl];
+                }
+#pragma unroll
+                for (int o = 0; o < kBY; ++o) {
+                    ra[o * rwh] = n[o] + wva[o];
+                    ra[o * rwh + 2 * pl] = d[o] + wa[o];
+                }
+            }
+            if (vb) {
+                float n[kBY], d[kBY];
+#pragma unroll
+                for (int o = 0; o < kBY; ++o) {
+                    n[o] = rb[o * rwh];
+                    d[o] = rb[o * rwh + 2 * pl];
+                }
+#pragma unroll
+                for (int o = 0; o < kBY; ++o) {
+                    rb[o * rwh] = n[o] + wvb[o];
+                    rb[o * rwh + 2 * pl] = d[o] + wb[o];
+                }
+            }
+            // Within one offset the lanes' and rows' targets y = x + delta are
+            // all different, so the read-add-writes above need no atomics; the
+            // next offset may hit a y another lane wrote here, so no LDS access
+            // may move across this point (a wave's LDS operations complete in
+            // issue order).
+            __asm__ volatile("" ::: "memory");
+            if (++dx > R) {
+                dx = -R;
+                ++dy;
+            }
+        }
+
+        // ---- reverse: the four waves' regions, added in wave order, to this item's slot
+        __syncthreads();
+        float *pt = a.part + ((size_t)sd.rp0 + lb) * (size_t)(2 * RH * RW);
+        for (int e = threadIdx.x; e < RH * RW; e += kBlock) {
+            const int r = e / RW, c = e - r * RW;
+            const int o = (c & 1) * pl + r * rwh + (c >> 1);
+            float n = rev[o], d = rev[o + 2 * pl];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) {
+                n += rev[w * 4 * pl + o];
+                d += rev[w * 4 * pl + o + 2 * pl];
+            }
+            reinterpret_cast<float2 *>(pt)[e] = make_float2(n, d);
+        }
+        // ---- forward: waves 1..3 park their sums in the (now free) region space, wave 0 adds
+        __syncthreads();
+        float *mg = rev;   // [3][4 * kBY][64]: lane-consecutive words
+        if (wave > 0) {
+            float *p = mg + (size_t)(wave - 1) * 4 * kBY * 64 + lane;
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                p[(4 * o + 0) * 64] = numa[o]; p[(4 * o + 1) * 64] = dena[o];
+                p[(4 * o + 2) * 64] = numb[o]; p[(4 * o + 3) * 64] = denb[o];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+                const float *p = mg + (size_t)w * 4 * kBY * 64 + lane;
+#pragma unroll
+                for (int o = 0; o < kBY; ++o) {
+                    numa[o] += p[(4 * o + 0) * 64]; dena[o] += p[(4 * o + 1) * 64];
+                    numb[o] += p[(4 * o + 2) * 64]; denb[o] += p[(4 * o + 3) * 64];
+                }
+            }
+            float2 *fo = a.fwd + sd.img0 + (size_t)i * plane;
+#pragma unroll
+            for (int o = 0; o < kBY; ++o) {
+                if (yb + o >= L) continue;
+                if (va) fo[(size_t)(yb + o) * L + xa] = make_float2(numa[o], dena[o]);
+                if (vb) fo[(size_t)(yb + o) * L + xa + 1] = make_float2(numb[o], denb[o]);
+            }
+        }
+    }
+    work_end(st);
+}
+
+// One direction of one pixel exactly as Eq. 8 states it (direct patch sums,
+// running minimum): the fallback where the unshifted weights underflow.
+__device__ float exact_side(const float *__restrict__ gi, const float *__restrict__ gj,
+                            const float *__restrict__ vj, int L, int S, int R, float nk, int r, int c) {
+    float Dm = INFINITY, num = 0.0f, den = 0.0f;
+    for (int dy = -R; dy <= R; ++dy) {
+        const int r2 = r + dy;
+        if (r2 < 0 || r2 >= L) continue;
+        for (int dx = -R; dx <= R; ++dx) {
+            const int c2 = c + dx;
+            if (c2 < 0 || c2 >= L) continue;
+            float D = 0.0f;
+            for (int py = -S; py <= S; ++py) {
+                const int ra = min(max(r + py, 0), L - 1), rb = min(max(r2 + py, 0), L - 1);
+                for (int px = -S; px <= S; ++px) {
+                    const int ca = min(max(c + px, 0), L - 1), cb = min(max(c2 + px, 0), L - 1);
+                    const float d = gi[(size_t)ra * L + ca] - gj[(size_t)rb * L + cb];
+                    D = fmaf(d, d, D);
+                }
+            }
+            online_add(D, vj[(size_t)r2 * L + c2], nk, Dm, num, den);
+        }
+    }
+    return num / den;
+}
+
+struct SymFinishArgs {
+    int S, R, TH;
+    float nk, cs, cn;
+    const float *guide, *value, *g;
+    const float2 *fwd;
+    const float *part;
+    float *out;
+    int clamp;
+    double *relpart;
+    int *nonfinite;
+};
+
+// Eq. 7 from the two directions of each pixel: the forward sums of the pair
+// (i, i+1) and the reverse sums of the pair (i-1, i) from every tile whose
+// region holds the pixel (tile rows, then columns, ascending).
+__global__ __launch_bounds__(kBlock) void k_tnlm_sym_finish(Batch bt, Stage st, SymFinishArgs a) {
+#pragma clang fp contract(off)
+    __shared__ double shred[kBlock];
+    __shared__ int sh_item;
+    const float tiny = 0x1p-60f;
+    const int S = a.S, R = a.R, TW = 32 - 2 * S, TH = a.TH;
+    const int RW = TW + 2 * R, RH = TH + 2 * R;
+    WorkIter it = work_begin(st);
+    int gb;
+    while (work_next(st, it, gb, &sh_item)) {
+        const int sidx = find_slice(st.pre, bt.ns, gb);
+        if (bt.skip && bt.skip[sidx]) continue;
+        const SliceDesc sd = bt.sl[sidx];
+        const int L = sd.L, N = sd.N;
+        const int ntx = (L + TW - 1) / TW, nty = (L + TH - 1) / TH, nt = ntx * nty;
+        const int lb = gb - st.pre[sidx];
+        const int tile_local = lb % nt, i = lb / nt;
+        const int x0 = (tile_local % ntx) * TW, y0 = (tile_local / ntx) * TH;
+        const int ip = (i - 1 + N) % N, in = (i + 1) % N;
+        const size_t plane = (size_t)L * L;
+        const float *gs = a.guide + sd.img0, *vs = a.value + sd.img0;
+        const float *gi = a.g + sd.img0 + (size_t)i * plane;
+        float *oi = a.out + sd.img0 + (size_t)i * plane;
+        const float2 *fw = a.fwd + sd.img0 + (size_t)i * plane;
+        const float *pp = a.part + ((size_t)sd.rp0 + (size_t)ip * nt) * (size_t)(2 * RH * RW);
+        double dd = 0.0, nn = 0.0;
+        bool bad = false;
+        for (int e = threadIdx.x; e < TW * TH; e += kBlock) {
+            const int r = y0 + e / TW, c = x0 + e % TW;
+            if (r >= L || c >= L) continue;
+            const size_t px = (size_t)r * L + c;
+            // tiles t whose region [t*T - R, t*T + T + R) holds the row / column:
+            // ceil((r - R - T + 1) / T) <= t <= floor((r + R) / T), the lower
+            // bound's numerator made positive by 64 T (R < 64 <= 64 T)
+            const int tylo = max(0, (r - R + 64 * TH) / TH - 64);
+            const int txlo = max(0, (c - R + 64 * TW) / TW - 64);
+            const int tyhi = min(nty - 1, (r + R) / TH), txhi = min(ntx - 1, (c + R) / TW);
+            float nr = 0.0f, dr = 0.0f;
+            for (int ty = tylo; ty <= tyhi; ++ty)
+                for (int tx = txlo; tx <= txhi; ++tx) {
+                    const int lr = r - (ty * TH - R), lc = c - (tx * TW - R);
+                    const float2 v = reinterpret_cast<const float2 *>(pp + (size_t)(ty * ntx + tx) * (2 * RH * RW))
+                        [lr * RW + lc];
+                    nr += v.x;
+                    dr += v.y;
+                }
+            const float2 F = fw[px];
+            const float Ar = dr >= tiny ? nr / dr
+                                        : exact_side(gs + (size_t)i * plane, gs + (size_t)ip * plane,
+                                                     vs + (size_t)ip * plane, L, S, R, a.nk, r, c);
+            const float Af = F.y >= tiny ? F.x / F.y
+                                         : exact_side(gs + (size_t)i * plane, gs + (size_t)in * plane,
+                                                      vs + (size_t)in * plane, L, S, R, a.nk, r, c);
+            float u = fmaf(a.cn, Ar + Af, a.cs * gi[px]);
+            if (a.clamp) u = fmaxf(u, 0.0f);
+            if (a.relpart) {
+                const double df = (double)u - (double)oi[px];
+                dd = fma(df, df, dd);
+                nn = fma((double)u, (double)u, nn);
+            }
+            bad |= !isfinite(u);
+            oi[px] = u;
+        }
+        if (bad && a.nonfinite) a.nonfinite[sidx] = 1;
+        if (a.relpart) {
+            dd = block_sum_256(dd, shred);
+            nn = block_sum_256(nn, shred);
+            if (threadIdx.x == 0) {
+                const long long blk = (long long)sd.rp0 + lb;
+                a.relpart[2 * blk] = dd;
+                a.relpart[2 * blk + 1] = nn;
+            }
+        }
+    }
+    work_end(st);
+}
+
+constexpr int kSymBY = 4;   // output rows per lane of the symmetric kernel
+
+// Row stride of one column-parity plane of a reverse region: at least half
+// the region's width, with 4 * stride = 16 (mod 32) so that bands 0, 1 (2, 3)
+// of a wave fall on opposite bank halves; the plain half width where that
+// would not fit. Also the LDS bytes of a block.
+static int sym_rwh(int patch, int window, bool same, size_t *lds_bytes) {
+    const int S = patch / 2, R = window / 2;
+    const int RW = 32 - 2 * S + 2 * R, RH = 4 * kSymBY + 2 * R;
+    const size_t ts = (size_t)(32 + 2 * R) * (4 * kSymBY + 2 * S + 2 * R) * (same ? 1 : 2);
+    int rwh = (RW + 1) / 2;
+    while (rwh % 8 != 4) ++rwh;
+    if ((ts + 16 * (size_t)RH * rwh) * sizeof(float) > 65536) rwh = (RW + 1) / 2;
+    const size_t need = std::max(ts + 16 * (size_t)RH * rwh, ts + (size_t)3 * 64 * 4 * kSymBY) * sizeof(float);
+    if (lds_bytes) *lds_bytes = need;
+    return rwh;
+}
+
+bool reg_sym_supported(int patch, int window) {
+    if (!reg_supported(patch, window)) return false;
+    size_t a = 0, b = 0;
+    sym_rwh(patch, window, true, &a);
+    sym_rwh(patch, window, false, &b);
+    return std::max(a, b) <= 65536;
+}
+
+size_t reg_sym_part_floats(int patch, int window) {
+    const int S = patch / 2, R = window / 2;
+    return 2 * (size_t)(32 - 2 * S + 2 * R) * (4 * kSymBY + 2 * R);
+}
+
+int reg_sym_rows_per_lane() { return kSymBY; }
+
+void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, const float *guide,
+                           const float *value, const float *g, float *out, int clamp, double *relpart,
+                           int *nonfinite, float2 *fwd, float *part, hipStream_t strm) {
+    if (st.total == 0) return;
+    size_t lds = 0;
+    SymArgs a;
+    a.R = p.window / 2;
+    a.rwh = sym_rwh(p.patch, p.window, value == guide, &lds);
+    a.nk = (float)(-1.4426950408889634 / ((double)p.h * (double)p.h));
+    a.guide = guide;
+    a.value = value;
+    a.fwd = fwd;
+    a.part = part;
+    switch (p.patch / 2) {
+        case 1: k_tnlm_sym<1, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        case 2: k_tnlm_sym<2, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        case 3: k_tnlm_sym<3, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+        default: k_tnlm_sym<4, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
+    }
+    SymFinishArgs f;
+    f.S = p.patch / 2;
+    f.R = p.window / 2;
+    f.TH = 4 * kSymBY;
+    f.nk = a.nk;
+    f.cs = (float)(1.0 / (1.0 + (double)p.mu_hat));
+    f.cn = (float)((double)p.mu_hat / (2.0 * (double)p.mu_hat + 2.0));
+    f.guide = guide;
+    f.value = value;
+    f.g = g;
+    f.fwd = fwd;
+    f.part = part;
+    f.out = out;
+    f.clamp = clamp;
+    f.relpart = relpart;
+    f.nonfinite = nonfinite;
+    k_tnlm_sym_finish<<<st.grid, kBlock, 0, strm>>>(b, st, f);
+}
+
 }  // namespace tnlm

@@ -15,6 +15,12 @@ from . import _native as nat
 from ._native import TnlmError, check
 
 
+def _ssd_mode(name):
+    if name not in nat.SSD_MODES:
+        raise ValueError(f"ssd_mode must be one of {sorted(nat.SSD_MODES)}, not {name!r}")
+    return nat.SSD_MODES[name]
+
+
 def _norm_device(device):
     d = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     return torch.device("cuda", torch.cuda.current_device()) if d.index is None else d
@@ -38,7 +44,7 @@ class Recon:
                          float(dgamma_rad), float(det_offset_bins), ang.ctypes.data_as(C.POINTER(C.c_double)))
         p = nat.Params(int(patch), int(window), float(h), float(mu_hat), float(beta), int(m1), int(m2),
                        int(max_outer), float(tol), nat.INIT_FBP_ALL if init == "fbp" else nat.INIT_USER,
-                       nat.SSD_FP32 if ssd_mode == "fp32" else nat.SSD_BF16_MFMA)
+                       _ssd_mode(ssd_mode))
         self.params = dict(patch=patch, window=window, h=h, mu_hat=mu_hat, beta=beta, m1=m1, m2=m2,
                            max_outer=max_outer, tol=tol, init=init, ssd_mode=ssd_mode)
         self._ctx = C.c_void_p()
@@ -185,7 +191,7 @@ class Batch:
         arr = (nat.Geometry * len(self.geoms))(*[_geom_struct(g, self._keep) for g in self.geoms])
         p = nat.Params(int(patch), int(window), float(h), float(mu_hat), float(beta), int(m1), int(m2),
                        int(max_outer), float(tol), nat.INIT_FBP_ALL if init == "fbp" else nat.INIT_USER,
-                       nat.SSD_FP32 if ssd_mode == "fp32" else nat.SSD_BF16_MFMA)
+                       _ssd_mode(ssd_mode))
         self.max_outer = int(max_outer)
         self._b = C.c_void_p()
         with torch.cuda.device(self.device):

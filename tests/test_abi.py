@@ -51,7 +51,8 @@ def _geom_params(**over):
     (dict(patch=4), -1), (dict(window=6), -1), (dict(window=17), -2), (dict(h=0.0), -1),
     (dict(mu_hat=-1.0), -1), (dict(beta=0.0), -1), (dict(m2_jacobi=0), -1), (dict(max_outer=0), -1),
     (dict(n_phases=0), -2), (dict(L=0), -2), (dict(n_bins=0), -2), (dict(pixel_mm=-1.0), -1),
-    (dict(sad_mm=10.0), -1), (dict(init=7), -1), (dict(tol_rel_update=-1.0), -1),
+    (dict(sad_mm=10.0), -1), (dict(init=7), -1), (dict(tol_rel_update=-1.0), -1), (dict(ssd_mode=3), -1),
+    (dict(L=32, patch=9, window=21, ssd_mode=2), -1),   # symmetric reuse: window 21 exceeds a block's LDS
 ])
 def test_init_rejects_bad_arguments(over, code):
     from paper_1009_1351_amd import _native as nat

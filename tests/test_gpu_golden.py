@@ -51,16 +51,19 @@ def report(tag, got, ref):
     return err, mx
 
 
-def test_regulariser_sweep_256():
+@pytest.mark.parametrize("ssd_mode", ["fp32", "fp32_sym"])
+def test_regulariser_sweep_256(ssd_mode):
     """One full-image regulariser sweep at the benchmark's shape: each of the
     persistent blocks handles several tiles here, so the tile loop and its LDS
-    reuse are compared element by element."""
+    reuse are compared element by element (per-phase kernel, and the
+    symmetric reuse of the phase pairs)."""
     ref = stored("sweep256")["f"].astype(np.float64)
     case, g = golden.sweep_input()
-    rc = recon_for(case.geom, patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat)
+    rc = recon_for(case.geom, patch=case.patch, window=case.window, h=case.h, mu_hat=case.mu_hat,
+                   ssd_mode=ssd_mode)
     gd = to_dev(g)
     out = to_host(rc.regularize(gd, gd, gd))
-    err, _ = report("sweep 10 x 256^2", out, ref)
+    err, _ = report(f"sweep 10 x 256^2 ({ssd_mode})", out, ref)
     assert err.max() < 1e-5
 
 
@@ -87,6 +90,17 @@ def test_trajectory_256_matches_oracle(name):
     np.testing.assert_allclose(hist, gold["hist"], rtol=2e-3)
 
 
+def test_trajectory_256_symmetric_matches_oracle():
+    """The low-dose 256^2 slice, 50 iterations, with the symmetric-reuse
+    regulariser: the same stored oracle result and the same bar."""
+    announce("trajectory c2c, symmetric reuse")
+    gold, case, f, k, hist = _solve_single("c2c", ssd_mode="fp32_sym")
+    err, _ = report("c2c 50 iterations (fp32_sym)", f, gold["f"].astype(np.float64))
+    assert k == int(gold["iters"]) == case.max_outer
+    assert err.max() < 1e-4
+    np.testing.assert_allclose(hist, gold["hist"], rtol=2e-3)
+
+
 def test_dose_cases_as_one_batch_match_oracle():
     """The three 256^2 dose cases solved together by the batched engine."""
     from paper_1009_1351_amd import Batch
@@ -105,24 +119,36 @@ def test_dose_cases_as_one_batch_match_oracle():
         assert k == c0.max_outer and err.max() < 1e-4
 
 
-def test_mixed_batch_slices_match_oracle():
+_MIXED = []
+
+
+def _mixed_batch_cases():
+    if not _MIXED:
+        _MIXED.extend(synth.make_case("C3", slice_index=s) for s in range(64))
+    return _MIXED
+
+
+@pytest.mark.parametrize("ssd_mode", ["fp32", "fp32_sym"])
+def test_mixed_batch_slices_match_oracle(ssd_mode):
     """The 64-slice mixed batch of the benchmark (L from 128 to 512, 40-360
     views, 1.5 L bins), 50 iterations in one batched solve; the slices the
     oracle ran (128^2 with 48 views, 256^2 with 56 views) are compared whole,
     and every slice's image must be finite and non-negative."""
     from paper_1009_1351_amd import Batch
     picks = {6: stored("c3s6"), 34: stored("c3s34")}
-    announce("mixed batch: 64 slices, 50 iterations")
-    cases = [synth.make_case("C3", slice_index=s) for s in range(64)]
+    announce(f"mixed batch: 64 slices, 50 iterations ({ssd_mode})")
+    cases = _mixed_batch_cases()
     c0 = cases[0]
-    bt = Batch([c.geom for c in cases], patch=7, window=15, h=c0.h, mu_hat=c0.mu_hat, max_outer=50)
+    bt = Batch([c.geom for c in cases], patch=7, window=15, h=c0.h, mu_hat=c0.mu_hat, max_outer=50,
+               ssd_mode=ssd_mode)
     ys = [to_dev(f32(c.y)) for c in cases]
     ws = [to_dev(f32(c.w)) for c in cases]
     fs, iters, _, sts, st = bt.solve(ys, ws)
     bt.close()
     assert st == 0 and all(k == 50 for k in iters)
     for s, g in picks.items():
-        err, _ = report(f"mixed batch slice {s} (L {cases[s].geom.L})", to_host(fs[s]), g["f"].astype(np.float64))
+        err, _ = report(f"mixed batch slice {s} (L {cases[s].geom.L}, {ssd_mode})", to_host(fs[s]),
+                        g["f"].astype(np.float64))
         assert err.max() < 1e-4
     for f in fs:
         assert bool(torch.isfinite(f).all()) and float(f.min()) >= 0.0

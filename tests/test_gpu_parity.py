@@ -258,8 +258,19 @@ def test_regularize_constant_fixed_point():
     rc = recon_for(small_geom(3, 45, 8, 16), patch=7, window=15, h=0.004, mu_hat=0.8)
     gd = to_dev(g)
     out = to_host(rc.regularize(gd, gd, gd))
-    # exact in real arithmetic; FP32 evaluation of num/den and two FMAs: <= 3 ulp
-    np.testing.assert_allclose(out, np.float32(0.0173), rtol=3.5e-7, atol=0)
+    # Exact in real arithmetic: every distance is 0, so every weight is
+    # exp2(0) = 1 and each side's weight sum is an integer <= 225 (exact in
+    # FP32). The only rounding is in the weighted sum of n <= W^2 = 225 equal
+    # positive terms, in whatever order or tree the kernel adds them:
+    # relative error <= gamma_(n-1), gamma_k = k u / (1 - k u) (Higham,
+    # Accuracy and Stability of Numerical Algorithms, Sec. 4.2). Six more
+    # roundings follow: the quotient, the sum of the two sides, the FP32
+    # constants 1/(1+mu) and mu/(2mu+2), the product with g and the final fma;
+    # gamma_(n-1+6) bounds the whole.
+    u = 2.0 ** -24
+    k = 15 * 15 - 1 + 6
+    bound = k * u / (1 - k * u)
+    np.testing.assert_allclose(out, np.float32(0.0173), rtol=bound, atol=0)
 
 
 def test_weights_normalised_via_unit_value():
