@@ -480,7 +480,9 @@ def summarize_counters(out_md, title, command, dirs):
                    mix (streams of independent FP32 FMAs reach 0.90, compare /
                    select / add 1.33, integer add / shift / xor 1.59)
       lanes      = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU)
-      MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (256 CUs x time cycles)
+      MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x time cycles): the
+                   counter adds the busy cycles of every SIMD's matrix core (it
+                   equals 16 cycles per 16x16x32 BF16 MFMA issued)
       LDS conflict cycles per LDS instruction = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS"""
     import csv
     from collections import defaultdict
@@ -523,7 +525,7 @@ def summarize_counters(out_md, title, command, dirs):
         out[-1] += " | ".join([
             frac(m.get("SQ_INSTS_VALU"), 256 * cyc if cyc else None),
             frac(m.get("SQ_THREAD_CYCLES_VALU"), 64 * m["SQ_ACTIVE_INST_VALU"] if m.get("SQ_ACTIVE_INST_VALU") else None),
-            frac(m.get("SQ_VALU_MFMA_BUSY_CYCLES"), 256 * cyc if cyc else None),
+            frac(m.get("SQ_VALU_MFMA_BUSY_CYCLES"), 1024 * cyc if cyc else None),
             frac(m.get("SQ_LDS_BANK_CONFLICT"), m.get("SQ_INSTS_LDS"))]) + " |"
     out.append("")
     open(os.path.join(ROOT, "profiles", out_md), "w").write("\n".join(out))
