@@ -404,11 +404,13 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, counters_command, 
     kind_ns = defaultdict(lambda: [0.0, 0])
     for r in rows:
         k = kind_of(r["Name"])
-        if k:
+        if k == "regularize_finish":   # the symmetric regulariser's second kernel: one launch with the first
+            kind_ns["regularize"][0] += float(r["TotalDurationNs"])
+        elif k:
             kind_ns[k][0] += float(r["TotalDurationNs"])
             kind_ns[k][1] += int(r["Calls"])
-    out += ["", "Average per launch by kind (all template instances), against the HIP-event figures "
-                "that bench.py measured in the same run:", "",
+    out += ["", "Average per launch by kind (all template instances; the symmetric regulariser's two kernels "
+                "as one launch), against the HIP-event figures that bench.py measured in the same run:", "",
             "| kind | launches | avg ms (trace) | avg ms (HIP events) |", "|---|---|---|---|"]
     rk = bj.get("roofline_kernels", {})
     for k, (ns, n) in sorted(kind_ns.items()):
