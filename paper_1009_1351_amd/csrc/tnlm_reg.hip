@@ -501,7 +501,9 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
         }
         for (int e = threadIdx.x; e < 16 * pl; e += kBlock) rev[e] = 0.0f;
 
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // the wave index as a wave-uniform value: the offset loop's bounds and
+        // the offsets' address parts then live in scalar registers
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const int l16 = lane & 15, band = lane >> 4;
         const int xa = x0 - S + 2 * l16;
         const int zbase = y0 + band * kBY - S;
@@ -532,69 +534,74 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
 
         const int ta = 2 * l16 + R, trb = band * kBY + R;
         const float nk = a.nk;
-        float *rw = rev + wave * 4 * pl;
+        // per-lane bases; each offset adds a wave-uniform part
+        const float *tgl = tg + trb * TCW + ta;                      // guide tile at (row, column) of x
+        const float *tvl = tv + (band * kBY + S + R) * TCW + ta;     // value tile at x's first output row
+        float *rwl = rev + wave * 4 * pl + (band * kBY + R) * rwh + l16;   // reverse region, x's first row
         const int k0 = wave * WW / 4, k1 = (wave + 1) * WW / 4;
         int dy = k0 / W - R, dx = k0 % W - R;
         for (int k = k0; k < k1; ++k) {
             // the neighbour's values at y (in bounds for every lane): read
             // first, so the distance arithmetic hides their latency
-            const float *vp = tv + (band * kBY + S + R + dy) * TCW + ta + dx;
+            const float *vp = tvl + dy * TCW + dx;
             float vya[kBY], vyb[kBY];
 #pragma unroll
             for (int o = 0; o < kBY; ++o) {
                 vya[o] = vp[o * TCW];
                 vyb[o] = vp[o * TCW + 1];
             }
-            float ha[NR], hb[NR];
-            const float *rowp = tg + (trb + dy) * TCW + ta + dx;
+            // squared differences of the lane's two columns over its BY + 2S
+            // rows; summed down the patch rows first (per column, in
+            // registers), then across the patch columns (DPP) for the BY
+            // output rows only
+            float ea[NR], eb[NR];
+            const float *rowp = tgl + dy * TCW + dx;
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 const float da = gia[q] - rowp[q * TCW];
                 const float db = gib[q] - rowp[q * TCW + 1];
-                const float eb = db * db;
-                hsum<S>(da * da, eb, fmaf(da, da, eb), ha[q], hb[q]);
+                ea[q] = da * da;
+                eb[q] = db * db;
             }
             const bool ca = va && (unsigned)(xa + dx) < (unsigned)L;
             const bool cb = vb && (unsigned)(xa + 1 + dx) < (unsigned)L;
-            // reverse region column of y = x + delta for column a (the b column
-            // is the next one, in the other parity plane); rows from band start
-            const int cy = 2 * l16 - S + dx + R;
-            const int par = cy & 1;
-            float *ra = rw + par * pl + (cy >> 1) + (band * kBY + dy + R) * rwh;
-            float *rb = rw + (par ^ 1) * pl + ((cy + 1) >> 1) + (band * kBY + dy + R) * rwh;
+            // reverse region column of y = x + delta: 2 l16 + c0 for column a,
+            // the next one (other parity plane) for b; c0 is wave-uniform
+            const int c0 = dx + R - S;
+            const int par = c0 & 1;
+            float *ra = rwl + par * pl + (c0 >> 1) + dy * rwh;
+            float *rb = rwl + (par ^ 1) * pl + ((c0 + 1) >> 1) + dy * rwh;
             float p2a[NR - 1], p2b[NR - 1];
 #pragma unroll
             for (int q = 0; q + 1 < NR; ++q) {
-                p2a[q] = ha[q] + ha[q + 1];
-                p2b[q] = hb[q] + hb[q + 1];
+                p2a[q] = ea[q] + ea[q + 1];
+                p2b[q] = eb[q] + eb[q + 1];
             }
             float wa[kBY], wva[kBY], wb[kBY], wvb[kBY];   // reverse terms, 0 for pairs outside the image
 #pragma unroll
             for (int o = 0; o < kBY; ++o) {
-                float Da = ha[o + 2 * S], Db = hb[o + 2 * S];
+                float Va = ea[o + 2 * S], Vb = eb[o + 2 * S];
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
-                    Da += p2a[o + 2 * q];
-                    Db += p2b[o + 2 * q];
+                    Va += p2a[o + 2 * q];
+                    Vb += p2b[o + 2 * q];
                 }
+                float Da, Db;
+                hsum<S>(Va, Vb, Va + Vb, Da, Db);
                 // both ends inside the image: y's row here, x's row too (rows of
                 // the last tile row past the image must not reach y's sums)
+                // A pair with an end outside takes an infinite distance, so its
+                // weight is exactly 0 and every sum below gains +0 (the staged
+                // values are finite): no branches.
                 const bool rv = (unsigned)(yb + o + dy) < (unsigned)L && yb + o < L;
-                wa[o] = wva[o] = wb[o] = wvb[o] = 0.0f;
-                if (rv && ca) {
-                    const float w = __builtin_amdgcn_exp2f(Da * nk);
-                    numa[o] = fmaf(w, vya[o], numa[o]);
-                    dena[o] += w;
-                    wa[o] = w;
-                    wva[o] = w * via[o];
-                }
-                if (rv && cb) {
-                    const float w = __builtin_amdgcn_exp2f(Db * nk);
-                    numb[o] = fmaf(w, vyb[o], numb[o]);
-                    denb[o] += w;
-                    wb[o] = w;
-                    wvb[o] = w * vib[o];
-                }
+                wa[o] = __builtin_amdgcn_exp2f((rv && ca ? Da : INFINITY) * nk);
+                wb[o] = __builtin_amdgcn_exp2f((rv && cb ? Db : INFINITY) * nk);
+                numa[o] = fmaf(wa[o], vya[o], numa[o]);
+                dena[o] += wa[o];
+                wva[o] = wa[o] * via[o];
+                numb[o] = fmaf(wb[o], vyb[o], numb[o]);
+                denb[o] += wb[o];
+                wvb[o] = wb[o] * vib[o];
             }
             // reverse sums: every row of a valid column lies inside the region
             // (adding 0 leaves a sum unchanged), so all reads go out before the
