@@ -16,10 +16,11 @@
 //     (dy <= 0 or dy > 0); its 64 lanes are 4 rows of 16 lanes, each lane
 //     owns 2 adjacent columns and 8 output rows;
 //   * per offset (dx, dy) a lane forms the squared differences E of its
-//     columns over 8 + 2S rows against its own phase's values held in
-//     registers, sums them across columns with DPP row shifts (16-lane rows,
-//     (32-2S)/32 of the lanes produce valid columns), and down its rows in
-//     registers -- all sums are of non-negative terms, no sliding subtraction;
+//     columns over BY + 2S rows against its own phase's values held in
+//     registers, sums them down the patch rows in registers and then, for its
+//     BY output rows, across the patch columns with DPP row shifts (16-lane
+//     rows, (32-2S)/32 of the lanes produce valid columns) -- all sums are of
+//     non-negative terms, no sliding subtraction;
 //   * the weights are accumulated with a running minimum distance (online
 //     normalisation: a new minimum rescales the running sums), so each pair
 //     costs one exp2 and the result equals Eq. 8 with the window-minimum shift;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
         }
     }
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nsel = wave & 1, half = wave >> 1;
     const int l16 = lane & 15, band = lane >> 4;
     const int xa = x0 - S + 2 * l16;
@@ -201,14 +202,17 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
         const int dy = half == 0 ? -kr : kr + 1;
         for (int kc = 0; kc <= 2 * R; ++kc) {
             const int dx = (kc & 1) ? (kc + 1) >> 1 : -(kc >> 1);
-            float ha[NR], hb[NR];
+            // squared differences of the lane's two columns, summed down the
+            // patch rows first, then across the patch columns (DPP) for the
+            // BY output rows only
+            float ea[NR], eb[NR];
             const float *rowp = TG + (trb + dy) * TCW + ta + dx;
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 const float da = gia[k] - rowp[k * TCW];
                 const float db = gib[k] - rowp[k * TCW + 1];
-                const float eb = db * db;
-                hsum<S>(da * da, eb, fmaf(da, da, eb), ha[k], hb[k]);
+                ea[k] = da * da;
+                eb[k] = db * db;
             }
             const bool ca = va && (unsigned)(xa + dx) < (unsigned)L;
             const bool cb = vb && (unsigned)(xa + 1 + dx) < (unsigned)L;
@@ -216,17 +220,19 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_reg(Batch bt, Stage st, RegArgs
             float p2a[NR - 1], p2b[NR - 1];
 #pragma unroll
             for (int k = 0; k + 1 < NR; ++k) {
-                p2a[k] = ha[k] + ha[k + 1];
-                p2b[k] = hb[k] + hb[k + 1];
+                p2a[k] = ea[k] + ea[k + 1];
+                p2b[k] = eb[k] + eb[k + 1];
             }
 #pragma unroll
             for (int o = 0; o < kBY; ++o) {
-                float Da = ha[o + 2 * S], Db = hb[o + 2 * S];
+                float Va = ea[o + 2 * S], Vb = eb[o + 2 * S];
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
-                    Da += p2a[o + 2 * j];
-                    Db += p2b[o + 2 * j];
+                    Va += p2a[o + 2 * j];
+                    Vb += p2b[o + 2 * j];
                 }
+                float Da, Db;
+                hsum<S>(Va, Vb, Va + Vb, Da, Db);
                 const bool rv = (unsigned)(yb + o + dy) < (unsigned)L;
                 if (rv && ca) online_add(Da, vp[o * TCW], nk, Dma[o], numa[o], dena[o]);
                 if (rv && cb) online_add(Db, vp[o * TCW + 1], nk, Dmb[o], numb[o], denb[o]);
@@ -538,8 +544,15 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
         const float *tgl = tg + trb * TCW + ta;                      // guide tile at (row, column) of x
         const float *tvl = tv + (band * kBY + S + R) * TCW + ta;     // value tile at x's first output row
         float *rwl = rev + wave * 4 * pl + (band * kBY + R) * rwh + l16;   // reverse region, x's first row
+        // offsets in column-major order (dy fastest): along a column run a
+        // lane's targets y move down one row per offset, so the reverse sums
+        // of its BY rows are carried in registers and a row goes to LDS once
+        // it has left the lane's window
         const int k0 = wave * WW / 4, k1 = (wave + 1) * WW / 4;
-        int dy = k0 / W - R, dx = k0 % W - R;
+        int dx = k0 / W - R, dy = k0 % W - R;
+        float san[kBY], sad[kBY], sbn[kBY], sbd[kBY];   // carried reverse sums, rows j + dy of columns a, b
+#pragma unroll
+        for (int j = 0; j < kBY; ++j) san[j] = sad[j] = sbn[j] = sbd[j] = 0.0f;
         for (int k = k0; k < k1; ++k) {
             // the neighbour's values at y (in bounds for every lane): read
             // first, so the distance arithmetic hides their latency
@@ -588,9 +601,9 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
                 }
                 float Da, Db;
                 hsum<S>(Va, Vb, Va + Vb, Da, Db);
-                // both ends inside the image: y's row here, x's row too (rows of
-                // the last tile row past the image must not reach y's sums)
-                // A pair with an end outside takes an infinite distance, so its
+                // Both ends inside the image (y's row here, x's row too: rows of
+                // the last tile row past the image must not reach y's sums); a
+                // pair with an end outside takes an infinite distance, so its
                 // weight is exactly 0 and every sum below gains +0 (the staged
                 // values are finite): no branches.
                 const bool rv = (unsigned)(yb + o + dy) < (unsigned)L && yb + o < L;
@@ -603,44 +616,67 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
                 denb[o] += wb[o];
                 wvb[o] = wb[o] * vib[o];
             }
-            // reverse sums: every row of a valid column lies inside the region
-            // (adding 0 leaves a sum unchanged), so all reads go out before the
-            // writes
+            // reverse sums: carried rows gain this offset's terms; row 0 of the
+            // window (y row dy) is final for this column run and goes to LDS
+            // (every row of a valid column lies inside the region; adding 0
+            // leaves a sum unchanged); at the run's end all rows go
+#pragma unroll
+            for (int j = 0; j < kBY; ++j) {
+                san[j] += wva[j];
+                sad[j] += wa[j];
+                sbn[j] += wvb[j];
+                sbd[j] += wb[j];
+            }
+            const bool run_end = dy == R || k + 1 == k1;   // wave-uniform
+            const int nflush = run_end ? kBY : 1;
             if (va) {
                 float n[kBY], d[kBY];
 #pragma unroll
-                for (int o = 0; o < kBY; ++o) {
-                    n[o] = ra[o * rwh];
-                    d[o] = ra[o * rwh + 2 * pl];
-                }
+                for (int j = 0; j < kBY; ++j)
+                    if (j < nflush) {
+                        n[j] = ra[j * rwh];
+                        d[j] = ra[j * rwh + 2 * pl];
+                    }
 #pragma unroll
-                for (int o = 0; o < kBY; ++o) {
-                    ra[o * rwh] = n[o] + wva[o];
-                    ra[o * rwh + 2 * pl] = d[o] + wa[o];
-                }
+                for (int j = 0; j < kBY; ++j)
+                    if (j < nflush) {
+                        ra[j * rwh] = n[j] + san[j];
+                        ra[j * rwh + 2 * pl] = d[j] + sad[j];
+                    }
             }
             if (vb) {
                 float n[kBY], d[kBY];
 #pragma unroll
-                for (int o = 0; o < kBY; ++o) {
-                    n[o] = rb[o * rwh];
-                    d[o] = rb[o * rwh + 2 * pl];
-                }
+                for (int j = 0; j < kBY; ++j)
+                    if (j < nflush) {
+                        n[j] = rb[j * rwh];
+                        d[j] = rb[j * rwh + 2 * pl];
+                    }
 #pragma unroll
-                for (int o = 0; o < kBY; ++o) {
-                    rb[o * rwh] = n[o] + wvb[o];
-                    rb[o * rwh + 2 * pl] = d[o] + wb[o];
-                }
+                for (int j = 0; j < kBY; ++j)
+                    if (j < nflush) {
+                        rb[j * rwh] = n[j] + sbn[j];
+                        rb[j * rwh + 2 * pl] = d[j] + sbd[j];
+                    }
+            }
+            // shift the window down one row (a new run starts empty)
+#pragma unroll
+            for (int j = 0; j < kBY; ++j) {
+                const bool keep = !run_end && j + 1 < kBY;
+                san[j] = keep ? san[j + 1 < kBY ? j + 1 : j] : 0.0f;
+                sad[j] = keep ? sad[j + 1 < kBY ? j + 1 : j] : 0.0f;
+                sbn[j] = keep ? sbn[j + 1 < kBY ? j + 1 : j] : 0.0f;
+                sbd[j] = keep ? sbd[j + 1 < kBY ? j + 1 : j] : 0.0f;
             }
             // Within one offset the lanes' and rows' targets y = x + delta are
-            // all different, so the read-add-writes above need no atomics; the
-            // next offset may hit a y another lane wrote here, so no LDS access
-            // may move across this point (a wave's LDS operations complete in
-            // issue order).
+            // all different, so the read-add-writes above need no atomics; a
+            // later offset may hit a y another lane wrote here, so no LDS
+            // access may move across this point (a wave's LDS operations
+            // complete in issue order).
             __asm__ volatile("" ::: "memory");
-            if (++dx > R) {
-                dx = -R;
-                ++dy;
+            if (++dy > R) {
+                dy = -R;
+                ++dx;
             }
         }
 
