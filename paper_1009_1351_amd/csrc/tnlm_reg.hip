@@ -460,6 +460,8 @@ void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int 
 // words) with a row stride that puts bands 0, 1 (and 2, 3) of a wave on
 // opposite halves of the 32 banks.
 
+constexpr int kSymBY = 4;   // output rows per lane of the symmetric kernel
+
 struct SymArgs {
     int R, rwh;          // window radius; row stride of one column-parity plane of a reverse region
     float nk;            // -log2(e) / h^2
@@ -730,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
 
 // One direction of one pixel exactly as Eq. 8 states it (direct patch sums,
 // running minimum): the fallback where the unshifted weights underflow.
-__device__ float exact_side(const float *__restrict__ gi, const float *__restrict__ gj,
+__device__ __noinline__ float exact_side(const float *__restrict__ gi, const float *__restrict__ gj,
                             const float *__restrict__ vj, int L, int S, int R, float nk, int r, int c) {
     float Dm = INFINITY, num = 0.0f, den = 0.0f;
     for (int dy = -R; dy <= R; ++dy) {
@@ -755,7 +757,7 @@ __device__ float exact_side(const float *__restrict__ gi, const float *__restric
 }
 
 struct SymFinishArgs {
-    int S, R, TH;
+    int R;
     float nk, cs, cn;
     const float *guide, *value, *g;
     const float2 *fwd;
@@ -769,12 +771,14 @@ struct SymFinishArgs {
 // Eq. 7 from the two directions of each pixel: the forward sums of the pair
 // (i, i+1) and the reverse sums of the pair (i-1, i) from every tile whose
 // region holds the pixel (tile rows, then columns, ascending).
+template <int S, int kBY>
 __global__ __launch_bounds__(kBlock) void k_tnlm_sym_finish(Batch bt, Stage st, SymFinishArgs a) {
 #pragma clang fp contract(off)
     __shared__ double shred[kBlock];
     __shared__ int sh_item;
     const float tiny = 0x1p-60f;
-    const int S = a.S, R = a.R, TW = 32 - 2 * S, TH = a.TH;
+    constexpr int TW = 32 - 2 * S, TH = 4 * kBY;   // compile-time: the index divisions become multiplies
+    const int R = a.R;
     const int RW = TW + 2 * R, RH = TH + 2 * R;
     WorkIter it = work_begin(st);
     int gb;
@@ -846,8 +850,6 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym_finish(Batch bt, Stage st, 
     work_end(st);
 }
 
-constexpr int kSymBY = 4;   // output rows per lane of the symmetric kernel
-
 // Row stride of one column-parity plane of a reverse region: at least half
 // the region's width, with 4 * stride = 16 (mod 32) so that bands 0, 1 (2, 3)
 // of a wave fall on opposite bank halves; the plain half width where that
@@ -899,9 +901,7 @@ void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, 
         default: k_tnlm_sym<4, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
     }
     SymFinishArgs f;
-    f.S = p.patch / 2;
     f.R = p.window / 2;
-    f.TH = 4 * kSymBY;
     f.nk = a.nk;
     f.cs = (float)(1.0 / (1.0 + (double)p.mu_hat));
     f.cn = (float)((double)p.mu_hat / (2.0 * (double)p.mu_hat + 2.0));
@@ -914,7 +914,12 @@ void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, 
     f.clamp = clamp;
     f.relpart = relpart;
     f.nonfinite = nonfinite;
-    k_tnlm_sym_finish<<<st.grid, kBlock, 0, strm>>>(b, st, f);
+    switch (p.patch / 2) {
+        case 1: k_tnlm_sym_finish<1, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
+        case 2: k_tnlm_sym_finish<2, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
+        case 3: k_tnlm_sym_finish<3, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
+        default: k_tnlm_sym_finish<4, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
+    }
 }
 
 }  // namespace tnlm
