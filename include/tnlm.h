@@ -63,9 +63,9 @@ enum { TNLM_INIT_FBP_ALL = 0, TNLM_INIT_USER = 1 };
  *                            unshifted exponential per pair serving both
  *                            directions; a pixel whose weight sum underflows
  *                            (below 2^-60) is recomputed exactly. Same result
- *                            as TNLM_SSD_FP32 up to rounding; needs one extra
- *                            image of forward sums and per-tile partial sums
- *                            (about 6 floats per image element). Window 21,
+ *                            as TNLM_SSD_FP32 up to rounding; needs forward
+ *                            and reverse partial sums (10 floats per image
+ *                            element at window <= 17, 14 at 19). Window 21,
  *                            and window 19 with patch 3, need more than
  *                            64 KiB of LDS per block and are rejected with
  *                            TNLM_E_INVALID_ARG. */

@@ -84,7 +84,7 @@ struct Engine {
     float *Q = nullptr, *ua = nullptr, *ub = nullptr;
     double *relpart = nullptr;
     float2 *symfwd = nullptr;   // symmetric-reuse regulariser: forward sums per image element
-    float *sympart = nullptr;   // and reverse partial sums per work item
+    float2 *sympart = nullptr;  // and reverse partial sums (image-shaped planes)
     double *cost_part = nullptr;   // [1024] partials of the data-term reduction
     int *flags = nullptr;   // [4][ns]: done, counter, nonfinite, spare
     int *queue = nullptr;   // [16]: work-item counters of the persistent stages (cleared by each launch)
@@ -506,7 +506,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     HIP_TRY(E.alloc(&E.relpart, 2 * (size_t)rpp));
     if (params->ssd_mode == TNLM_SSD_FP32_SYMMETRIC) {
         HIP_TRY(E.alloc(&E.symfwd, E.nimg));
-        HIP_TRY(E.alloc(&E.sympart, (size_t)rpp * reg_sym_part_floats(params->patch, params->window)));
+        HIP_TRY(E.alloc(&E.sympart, (size_t)reg_sym_planes(params->patch, params->window) * E.nimg));
     }
     HIP_TRY(E.alloc(&E.flags, 4 * (size_t)ns));
     HIP_TRY(E.alloc(&E.cost_part, 1024));
@@ -568,7 +568,7 @@ static void enqueue_regularize(Engine *E, const Batch &bt, float *f, bool record
             TIMED(E, K_REGULARIZE,
                   launch_regularize_sym(bt, E->st_reg, E->rp, guide, val, g, dst, last ? 1 : 0,
                                         last && record ? E->relpart : nullptr, E->nonfinite(), E->symfwd,
-                                        E->sympart, E->cur));
+                                        E->sympart, E->nimg, E->cur));
         else
             TIMED(E, K_REGULARIZE,
                   launch_regularize(bt, E->st_reg, E->rp, E->rows_per_lane, guide, val, g, dst, last ? 1 : 0,
@@ -996,7 +996,7 @@ extern "C" tnlm_status tnlm_regularize(tnlm_ctx *ctx, const float *d_guide, cons
     else if (E->prm.ssd_mode == TNLM_SSD_FP32_SYMMETRIC)
         TIMED(E, K_REGULARIZE,
               launch_regularize_sym(E->batch, E->st_reg, E->rp, d_guide, d_value, d_g, d_out, clamp ? 1 : 0, nullptr,
-                                    nullptr, E->symfwd, E->sympart, E->stream));
+                                    nullptr, E->symfwd, E->sympart, E->nimg, E->stream));
     else
         TIMED(E, K_REGULARIZE,
               launch_regularize(E->batch, E->st_reg, E->rp, E->rows_per_lane, d_guide, d_value, d_g, d_out,

@@ -220,11 +220,11 @@ bool reg_mfma_supported(int patch, int window);
 // symmetric reuse of §2.3 (ssd_mode FP32_SYMMETRIC): one pass over the
 // unordered phase pairs, then the per-pixel combination (two launches)
 bool reg_sym_supported(int patch, int window);
-size_t reg_sym_part_floats(int patch, int window);   // reverse partial floats per work item
+int reg_sym_planes(int patch, int window);   // image-shaped planes of reverse partial sums
 int reg_sym_rows_per_lane();
 void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, const float *guide,
                            const float *value, const float *g, float *out, int clamp, double *relpart,
-                           int *nonfinite, float2 *fwd, float *part, hipStream_t strm);
+                           int *nonfinite, float2 *fwd, float2 *part, size_t nimg, hipStream_t strm);
 void launch_regularize_mfma(const Batch &b, const Stage &st, const RegParams &p, const float *guide,
                             const float *value, const float *g, float *out, int clamp, double *relpart,
                             int *nonfinite, hipStream_t strm);

@@ -442,7 +442,11 @@ void launch_regularize(const Batch &b, const Stage &st, const RegParams &p, int 
 //     value_i(x), added into an LDS region covering T grown by the window
 //     radius; the pixels of that region near its rim also receive terms from
 //     the neighbouring tiles, so the block writes the region's sums out and a
-//     second kernel adds the (at most four) tiles' sums of each pixel.
+//     second kernel adds the (at most four) tiles' sums of each pixel. The
+//     sums go to image-shaped planes, one per residue class (ty mod my, tx mod
+//     mx) of the tile's position, with my, mx the number of tiles whose
+//     regions can hold a pixel along y and x: regions of one class never
+//     overlap, every write and every read streams along image rows.
 // One exponential and one distance per pair of directions, against two of
 // each when every phase computes both neighbours itself. The weights are not
 // shifted by the per-pixel minimum, which no single pass can know for the
@@ -467,7 +471,9 @@ struct SymArgs {
     float nk;            // -log2(e) / h^2
     const float *guide, *value;
     float2 *fwd;         // [image elements]: forward (sum w v, sum w) of phase i toward i+1
-    float *part;         // [work items][RH][RW][2]: reverse (sum w v, sum w) of each tile's region
+    float2 *part;        // [my * mx][image elements]: reverse (sum w v, sum w) of the tiles' regions
+    size_t nimg;         // image elements of the batch (stride of a plane)
+    int my, mx;          // region-class counts along y and x
 };
 
 template <int S, int kBY>
@@ -682,19 +688,25 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym(Batch bt, Stage st, SymArgs
             }
         }
 
-        // ---- reverse: the four waves' regions, added in wave order, to this item's slot
+        // ---- reverse: the four waves' regions, added in wave order, into the
+        // plane of this tile's class at phase j's elements (inside the image)
         __syncthreads();
-        float *pt = a.part + ((size_t)sd.rp0 + lb) * (size_t)(2 * RH * RW);
-        for (int e = threadIdx.x; e < RH * RW; e += kBlock) {
-            const int r = e / RW, c = e - r * RW;
-            const int o = (c & 1) * pl + r * rwh + (c >> 1);
-            float n = rev[o], d = rev[o + 2 * pl];
+        {
+            const int ty = y0 / TH, tx = x0 / TW;
+            float2 *pt = a.part + (size_t)((ty % a.my) * a.mx + tx % a.mx) * a.nimg + sd.img0 + (size_t)j * plane;
+            for (int e = threadIdx.x; e < RH * RW; e += kBlock) {
+                const int r = e / RW, c = e - r * RW;
+                const int Y = y0 - R + r, X = x0 - R + c;
+                if ((unsigned)Y >= (unsigned)L || (unsigned)X >= (unsigned)L) continue;
+                const int o = (c & 1) * pl + r * rwh + (c >> 1);
+                float n = rev[o], d = rev[o + 2 * pl];
 #pragma unroll
-            for (int w = 1; w < 4; ++w) {
-                n += rev[w * 4 * pl + o];
-                d += rev[w * 4 * pl + o + 2 * pl];
+                for (int w = 1; w < 4; ++w) {
+                    n += rev[w * 4 * pl + o];
+                    d += rev[w * 4 * pl + o + 2 * pl];
+                }
+                pt[(size_t)Y * L + X] = make_float2(n, d);
             }
-            reinterpret_cast<float2 *>(pt)[e] = make_float2(n, d);
         }
         // ---- forward: waves 1..3 park their sums in the (now free) region space, wave 0 adds
         __syncthreads();
@@ -761,7 +773,9 @@ struct SymFinishArgs {
     float nk, cs, cn;
     const float *guide, *value, *g;
     const float2 *fwd;
-    const float *part;
+    const float2 *part;
+    size_t nimg;
+    int my, mx;
     float *out;
     int clamp;
     double *relpart;
@@ -797,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym_finish(Batch bt, Stage st, 
         const float *gi = a.g + sd.img0 + (size_t)i * plane;
         float *oi = a.out + sd.img0 + (size_t)i * plane;
         const float2 *fw = a.fwd + sd.img0 + (size_t)i * plane;
-        const float *pp = a.part + ((size_t)sd.rp0 + (size_t)ip * nt) * (size_t)(2 * RH * RW);
+        const float2 *pp = a.part + sd.img0 + (size_t)i * plane;   // phase i's elements of plane 0
         double dd = 0.0, nn = 0.0;
         bool bad = false;
         for (int e = threadIdx.x; e < TW * TH; e += kBlock) {
@@ -813,9 +827,7 @@ __global__ __launch_bounds__(kBlock) void k_tnlm_sym_finish(Batch bt, Stage st, 
             float nr = 0.0f, dr = 0.0f;
             for (int ty = tylo; ty <= tyhi; ++ty)
                 for (int tx = txlo; tx <= txhi; ++tx) {
-                    const int lr = r - (ty * TH - R), lc = c - (tx * TW - R);
-                    const float2 v = reinterpret_cast<const float2 *>(pp + (size_t)(ty * ntx + tx) * (2 * RH * RW))
-                        [lr * RW + lc];
+                    const float2 v = pp[(size_t)((ty % a.my) * a.mx + tx % a.mx) * a.nimg + px];
                     nr += v.x;
                     dr += v.y;
                 }
@@ -874,16 +886,25 @@ bool reg_sym_supported(int patch, int window) {
     return std::max(a, b) <= 65536;
 }
 
-size_t reg_sym_part_floats(int patch, int window) {
-    const int S = patch / 2, R = window / 2;
-    return 2 * (size_t)(32 - 2 * S + 2 * R) * (4 * kSymBY + 2 * R);
+// Region classes along y and x: the number of tiles whose regions (the tile
+// grown by R) can hold one pixel.
+static void sym_classes(int patch, int window, int &my, int &mx) {
+    const int S = patch / 2, R = window / 2, TW = 32 - 2 * S, TH = 4 * kSymBY;
+    my = (TH + 2 * R + TH - 1) / TH;
+    mx = (TW + 2 * R + TW - 1) / TW;
+}
+
+int reg_sym_planes(int patch, int window) {
+    int my, mx;
+    sym_classes(patch, window, my, mx);
+    return my * mx;
 }
 
 int reg_sym_rows_per_lane() { return kSymBY; }
 
 void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, const float *guide,
                            const float *value, const float *g, float *out, int clamp, double *relpart,
-                           int *nonfinite, float2 *fwd, float *part, hipStream_t strm) {
+                           int *nonfinite, float2 *fwd, float2 *part, size_t nimg, hipStream_t strm) {
     if (st.total == 0) return;
     size_t lds = 0;
     SymArgs a;
@@ -894,6 +915,8 @@ void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, 
     a.value = value;
     a.fwd = fwd;
     a.part = part;
+    a.nimg = nimg;
+    sym_classes(p.patch, p.window, a.my, a.mx);
     switch (p.patch / 2) {
         case 1: k_tnlm_sym<1, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
         case 2: k_tnlm_sym<2, kSymBY><<<st.grid, kBlock, lds, strm>>>(b, st, a); break;
@@ -910,6 +933,9 @@ void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, 
     f.g = g;
     f.fwd = fwd;
     f.part = part;
+    f.nimg = nimg;
+    f.my = a.my;
+    f.mx = a.mx;
     f.out = out;
     f.clamp = clamp;
     f.relpart = relpart;
