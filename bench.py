@@ -367,7 +367,7 @@ def quality_leg(torch, dev, iters=50):
 
 # ------------------------------------------------------- profile summaries
 KIND_OF = {"k_project<": "project", "k_backproject(": "backproject", "k_tnlm_reg<": "regularize",
-           "k_tnlm_reg_mfma<": "regularize_bf16", "k_tnlm_sym<": "regularize", "k_tnlm_sym_finish(": "regularize_finish",
+           "k_tnlm_reg_mfma<": "regularize_bf16", "k_tnlm_sym<": "regularize", "k_tnlm_sym_finish": "regularize_finish",
            "k_transpose(": "transpose"}
 
 
