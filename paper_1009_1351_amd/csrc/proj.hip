@@ -557,22 +557,44 @@ __device__ __forceinline__ float fan_atan(float t) {
 
 // Candidate loop of one lane and view with the direction signs of all
 // candidate rays fixed (XP: T_x grows with the plane index; YP likewise):
-// planes c, c+1, c+2 (and r, r+1, r+2) are evaluated once and take the lo or
-// hi role of each pixel by the signs.
+// planes c, c+1, c+2 (and r, r+1, r+2) are evaluated once. With the signs
+// known, the ray meets the 2 x 2 square in order: it enters at tin = max of
+// the entry planes into the corner pixel on the entry sides, crosses the
+// middle lines x1 and y1 (clamped into [tin, tout]), and leaves at tout =
+// min of the exit planes from the opposite corner pixel; between min(x1, y1)
+// and max(x1, y1) it is in the neighbour of the entry pixel across the line
+// crossed first. Each length is the same difference of the same two plane
+// values as the pixel's clip min(hi planes) - max(lo planes), and a pixel
+// the ray misses gets +0, so the sums are those of the clips bit for bit
+// (the forward walk's entries).
+template <int R, int C>
+__device__ __forceinline__ float &blk(float &a00, float &a01, float &a10, float &a11) {
+    if constexpr (R == 0) return C == 0 ? a00 : a01;
+    else return C == 0 ? a10 : a11;
+}
+
 template <bool XP, bool YP>
 __device__ __forceinline__ void bp_block_ray(const float4 A, const float qb, float fc0, float fr0, float &a00,
                                              float &a01, float &a10, float &a11) {
     const float fc1 = fc0 + 1.0f, fc2 = fc0 + 2.0f, fr1 = fr0 + 1.0f, fr2 = fr0 + 2.0f;
     const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
     const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
-    const float xl0 = XP ? X0 : X1, xh0 = XP ? X1 : X0;   // column c
-    const float xl1 = XP ? X1 : X2, xh1 = XP ? X2 : X1;   // column c + 1
-    const float yl0 = YP ? Y0 : Y1, yh0 = YP ? Y1 : Y0;   // row r
-    const float yl1 = YP ? Y1 : Y2, yh1 = YP ? Y2 : Y1;   // row r + 1
-    a00 = fmaf(fmaxf(fminf(xh0, yh0) - fmaxf(xl0, yl0), 0.0f), qb, a00);
-    a01 = fmaf(fmaxf(fminf(xh1, yh0) - fmaxf(xl1, yl0), 0.0f), qb, a01);
-    a10 = fmaf(fmaxf(fminf(xh0, yh1) - fmaxf(xl0, yl1), 0.0f), qb, a10);
-    a11 = fmaf(fmaxf(fminf(xh1, yh1) - fmaxf(xl1, yl1), 0.0f), qb, a11);
+    const float tin = fmaxf(XP ? X0 : X2, YP ? Y0 : Y2);
+    const float tout = fmaxf(fminf(XP ? X2 : X0, YP ? Y2 : Y0), tin);   // tin when the ray misses the square
+    const float x1 = __builtin_amdgcn_fmed3f(tin, X1, tout);
+    const float y1 = __builtin_amdgcn_fmed3f(tin, Y1, tout);
+    const float a = fminf(x1, y1), b = fmaxf(x1, y1);
+    const float lmid = b - a;
+    const bool xfirst = x1 < y1;
+    constexpr int ci = XP ? 0 : 1, ri = YP ? 0 : 1;   // entry pixel
+    float &ain = blk<ri, ci>(a00, a01, a10, a11);
+    float &aout = blk<1 - ri, 1 - ci>(a00, a01, a10, a11);
+    float &ax = blk<ri, 1 - ci>(a00, a01, a10, a11);   // across the x line from the entry pixel
+    float &ay = blk<1 - ri, ci>(a00, a01, a10, a11);   // across the y line
+    ain = fmaf(a - tin, qb, ain);
+    ax = fmaf(xfirst ? lmid : 0.0f, qb, ax);
+    ay = fmaf(xfirst ? 0.0f : lmid, qb, ay);
+    aout = fmaf(tout - b, qb, aout);
 }
 
 // Two candidates per pass, both requested before either is used; an odd last
