@@ -45,6 +45,18 @@ __device__ __forceinline__ void chunk_range(long long n, int chunk, int nchunk, 
     hi = std::min(n, lo + per);
 }
 
+// Elements [n0, n1) (indices into arrays that start 16-byte aligned) by the
+// block: the aligned middle four at a time (16-byte accesses), the at most
+// three elements before and after it one at a time.
+template <class V, class S>
+__device__ __forceinline__ void vec_range(long long n0, long long n1, V vec4, S one) {
+    const long long v0 = std::min(n1, (n0 + 3) & ~3LL);
+    const long long v1 = std::max(v0, n1 & ~3LL);
+    if ((long long)threadIdx.x < v0 - n0) one(n0 + threadIdx.x);
+    if ((long long)threadIdx.x < n1 - v1) one(v1 + threadIdx.x);
+    for (long long k = v0 + 4 * (long long)threadIdx.x; k < v1; k += 4 * kBlock) vec4(k);
+}
+
 __global__ void k_sqrt(const float *__restrict__ w, float *__restrict__ sw, size_t n) {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
         sw[k] = sqrtf(fmaxf(w[k], 0.0f));
@@ -103,15 +115,42 @@ __global__ __launch_bounds__(kBlock) void k_cgls_update(Batch bt, Stage st, Cgls
         long long lo, hi;
         chunk_range(nimg + nsino, it.chunk, it.nchunk, lo, hi);
         const long long ib = sd.img0 + (long long)it.i * nimg, sbase = sd.sino0 + (long long)it.i * nsino;
-        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) {
-            if (k < nimg) {
-                cb.u[ib + k] = fmaf(a, cb.s[ib + k], cb.u[ib + k]);
-            } else {
-                const long long e = sbase + (k - nimg);
-                const float rv = fmaf(-a, cb.q[e], cb.r[e]);
-                cb.r[e] = rv;
-                cb.rw[e] = cb.sw[e] * rv;
-            }
+        float *__restrict__ u = cb.u;
+        const float *__restrict__ sv = cb.s;
+        if (lo < nimg)
+            vec_range(
+                ib + lo, ib + std::min(hi, nimg),
+                [&](long long k) {
+                    const float4 s4 = *reinterpret_cast<const float4 *>(sv + k);
+                    float4 u4 = *reinterpret_cast<const float4 *>(u + k);
+                    u4.x = fmaf(a, s4.x, u4.x);
+                    u4.y = fmaf(a, s4.y, u4.y);
+                    u4.z = fmaf(a, s4.z, u4.z);
+                    u4.w = fmaf(a, s4.w, u4.w);
+                    *reinterpret_cast<float4 *>(u + k) = u4;
+                },
+                [&](long long k) { u[k] = fmaf(a, sv[k], u[k]); });
+        if (hi > nimg) {
+            float *__restrict__ r = cb.r, *__restrict__ rw = cb.rw;
+            const float *__restrict__ q = cb.q, *__restrict__ sw = cb.sw;
+            vec_range(
+                sbase + std::max(lo, nimg) - nimg, sbase + hi - nimg,
+                [&](long long e) {
+                    const float4 q4 = *reinterpret_cast<const float4 *>(q + e);
+                    const float4 w4 = *reinterpret_cast<const float4 *>(sw + e);
+                    float4 r4 = *reinterpret_cast<const float4 *>(r + e);
+                    r4.x = fmaf(-a, q4.x, r4.x);
+                    r4.y = fmaf(-a, q4.y, r4.y);
+                    r4.z = fmaf(-a, q4.z, r4.z);
+                    r4.w = fmaf(-a, q4.w, r4.w);
+                    *reinterpret_cast<float4 *>(r + e) = r4;
+                    *reinterpret_cast<float4 *>(rw + e) = make_float4(w4.x * r4.x, w4.y * r4.y, w4.z * r4.z, w4.w * r4.w);
+                },
+                [&](long long e) {
+                    const float rv = fmaf(-a, q[e], r[e]);
+                    r[e] = rv;
+                    rw[e] = sw[e] * rv;
+                });
         }
     }
 }
@@ -136,7 +175,20 @@ __global__ __launch_bounds__(kBlock) void k_cgls_direction(Batch bt, Stage st, C
         long long lo, hi;
         chunk_range(nimg, it.chunk, it.nchunk, lo, hi);
         const long long ib = sd.img0 + (long long)it.i * nimg;
-        for (long long k = lo + threadIdx.x; k < hi; k += kBlock) cb.s[ib + k] = fmaf(bc, cb.s[ib + k], cb.t[ib + k]);
+        float *__restrict__ sv = cb.s;
+        const float *__restrict__ tv = cb.t;
+        vec_range(
+            ib + lo, ib + hi,
+            [&](long long k) {
+                const float4 t4 = *reinterpret_cast<const float4 *>(tv + k);
+                float4 s4 = *reinterpret_cast<const float4 *>(sv + k);
+                s4.x = fmaf(bc, s4.x, t4.x);
+                s4.y = fmaf(bc, s4.y, t4.y);
+                s4.z = fmaf(bc, s4.z, t4.z);
+                s4.w = fmaf(bc, s4.w, t4.w);
+                *reinterpret_cast<float4 *>(sv + k) = s4;
+            },
+            [&](long long k) { sv[k] = fmaf(bc, sv[k], tv[k]); });
     }
 }
 
