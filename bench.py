@@ -124,8 +124,8 @@ def make_cases(specs, workers=None):
 def cpu_baseline(c3_cases):
     """The FP64 oracle on the host cores: one outer iteration (FBP start) of
     two slices of the mixed batch (the smallest-view 128^2 and 256^2 slices),
-    on all the threads this process may use, and of the 128^2 slice on one
-    thread."""
+    on all the threads this process may use (and on 8 when it may use more),
+    and of the 128^2 slice on one thread."""
     import oracle
     oracle.build()
     from oracle import _lib_threads
@@ -150,10 +150,16 @@ def cpu_baseline(c3_cases):
         units, dt = run(picks)
     with _lib_threads(1):
         u1, d1 = run(picks[:1])
+    out8 = None
+    if threads > 8:
+        with _lib_threads(8):
+            u8, d8 = run(picks)
+        out8 = {"value": u8 / d8, "cores": 8, "sample": f"the same 2 slices, {d8:.1f} s"}
     shapes = ", ".join(f"{c.geom.L}^2 x {c.geom.n_views} views x {c.geom.n_bins} bins" for c in picks)
     return {"value": units / dt, "unit": "phase-pixel*iters/s", "cores": threads, "kind": "oracle",
             "sample": f"one outer iteration (CGLS x3 + regulariser, FBP start) of 2 of the 64 slices ({shapes}); "
                       f"{dt:.1f} s on {threads} threads",
+            "eight_threads": out8,
             "single_thread": {"value": u1 / d1, "cores": 1,
                               "sample": f"the {picks[0].geom.L}^2 slice alone, {d1:.1f} s"}}
 
