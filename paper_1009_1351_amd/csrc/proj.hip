@@ -443,7 +443,7 @@ void launch_transpose(const Batch &b, const Stage &st, const float *f, float *fP
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_project(Batch bt, Stage st, const float *__restrict__ f,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_project(Batch bt, Stage st, const float *__restrict__ f,
                                                     const float *__restrict__ fT, const float *__restrict__ y,
                                                     const float *__restrict__ sw, float *__restrict__ out,
                                                     float *__restrict__ out2, double *__restrict__ partials) {
@@ -628,7 +628,7 @@ int bp_blocks(const SliceDesc &s) {
     return s.N * t * t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_backproject(Batch bt, Stage st, const float *__restrict__ q,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_backproject(Batch bt, Stage st, const float *__restrict__ q,
                                                         float *__restrict__ fout, double *__restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int sh_item;
