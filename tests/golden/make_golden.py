@@ -10,8 +10,9 @@ Names and what each file holds (float32 images, float64 histories):
   sweep256        one regulariser sweep (Eq. 8 weights over a 15x15 window of
                   phases i+-1 with 7x7 patches, one Gauss-Jacobi sweep of
                   Eq. 7, positivity) of a 10 x 256^2 stack
-  c3s6, c3s34     two slices of the 64-slice mixed batch (128^2 with 48 views,
-                  256^2 with 56 views; bins 1.5 L), 50 outer iterations
+  c3s6, c3s34,    four slices of the 64-slice mixed batch, one per image side
+  c3s4, c3s16     (128^2 with 48 views, 256^2 with 56, 384^2 with 61, 512^2
+                  with 48; bins 1.5 L), 50 outer iterations
   c4s0            slice 0 of the 512^2 precision workload (120 views x 720
                   bins), 50 outer iterations
   c1tol           the 64^2 workload solved from the FBP of all phases until
@@ -47,6 +48,8 @@ TRAJECTORIES = {
     "c2c": ("C2c", 0),
     "c3s6": ("C3", 6),
     "c3s34": ("C3", 34),
+    "c3s4": ("C3", 4),
+    "c3s16": ("C3", 16),
     "c4s0": ("C4", 0),
     "c1tol": ("C1", 0),
 }
@@ -127,4 +130,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["sweep256", "c2c", "c2b", "c3s6", "c3s34", "c2a", "c4s0", "c1tol"])
+    main(sys.argv[1:] or ["sweep256", "c2c", "c2b", "c3s6", "c3s34", "c2a", "c4s0", "c1tol", "c3s4", "c3s16"])

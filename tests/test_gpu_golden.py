@@ -132,10 +132,11 @@ def _mixed_batch_cases():
 def test_mixed_batch_slices_match_oracle(ssd_mode):
     """The 64-slice mixed batch of the benchmark (L from 128 to 512, 40-360
     views, 1.5 L bins), 50 iterations in one batched solve; the slices the
-    oracle ran (128^2 with 48 views, 256^2 with 56 views) are compared whole,
-    and every slice's image must be finite and non-negative."""
+    oracle ran, one of each image size (128^2 with 48 views, 256^2 with 56,
+    384^2 with 61, 512^2 with 48), are compared whole, and every slice's image
+    must be finite and non-negative."""
     from paper_1009_1351_amd import Batch
-    picks = {6: stored("c3s6"), 34: stored("c3s34")}
+    picks = {s: stored(f"c3s{s}") for s in (4, 6, 16, 34)}
     announce(f"mixed batch: 64 slices, 50 iterations ({ssd_mode})")
     cases = _mixed_batch_cases()
     c0 = cases[0]
