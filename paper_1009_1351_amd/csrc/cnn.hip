@@ -34,10 +34,14 @@ constexpr int kLdsK = 40;  // padded K stride in LDS (elements): 80 bytes, 16-by
 // forward convolution (also used for the input gradient)
 // ---------------------------------------------------------------------------
 
+// KS: the kernel size when known at compile time (1 or 3), 0 for any (a.ks).
+template <int KS>
 __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
+    static_assert(kT == 64 && kBlock == 4 * kT && kKC == 32, "one pixel and 8 K-values per thread in staging");
     __shared__ __attribute__((aligned(16))) bf16b sA[kT * kLdsK];
     __shared__ __attribute__((aligned(16))) bf16b sB[kT * kLdsK];
-    const int HW = a.H * a.W, K = a.Cin * a.ks * a.ks, ks2 = a.ks * a.ks, pad = a.ks / 2;
+    const int ks = KS > 0 ? KS : a.ks, ks2 = ks * ks, pad = ks / 2;
+    const int HW = a.H * a.W, K = a.Cin * ks2;
     const int p0 = blockIdx.x * kT, co0 = blockIdx.y * kT, nimg = blockIdx.z;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave >> 1, wn = wave & 1;
@@ -47,6 +51,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
         for (int j = 0; j < 2; ++j) acc[i][j] = (f4_t){0.0f, 0.0f, 0.0f, 0.0f};
     const bf16b *inb = a.in + ((size_t)nimg * a.in_ct + a.in_c0) * HW;
     const bf16b *mb = a.mask ? a.mask + ((size_t)nimg * a.mask_ct + a.mask_c0) * HW : nullptr;
+    // im2col staging: pixel p0 + pr and K-values [8 kq, 8 kq + 8) of each chunk
+    const int pr = threadIdx.x & (kT - 1), kq = threadIdx.x >> 6;
+    const bool pix = p0 + pr < HW;
+    const int ypix = pix ? (p0 + pr) / a.W : 0, xpix = pix ? p0 + pr - ypix * a.W : 0;
     for (int kc = 0; kc < K; kc += kKC) {
         // A: weights rows co0.., K columns kc..
         for (int e = threadIdx.x; e < kT * kKC; e += kBlock) {
@@ -54,22 +62,35 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
             const int co = co0 + r, k = kc + c;
             sA[r * kLdsK + c] = (co < a.Cout && k < K) ? a.w[(size_t)co * K + k] : (bf16b)0;
         }
-        // B: im2col, stored [pixel][k]
-        for (int e = threadIdx.x; e < kT * kKC; e += kBlock) {
-            const int pr = e / kKC, c = e - pr * kKC;
-            const int p = p0 + pr, k = kc + c;
-            bf16b v = 0;
-            if (p < HW && k < K) {
-                const int ci = k / ks2, kk = k - ci * ks2;
-                const int ky = kk / a.ks, kx = kk - ky * a.ks;
-                const int y = p / a.W + ky - pad, x = p % a.W + kx - pad;
-                if ((unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W) {
-                    const size_t off = (size_t)ci * HW + (size_t)y * a.W + x;
-                    v = inb[off];
-                    if (mb && !(b2f(mb[off]) > 0.0f)) v = 0;
+        // B: im2col, stored [pixel][k]; the thread's 8 K-values of its pixel
+        // (consecutive lanes on consecutive pixels), written as one 16-byte store
+        {
+            int k = kc + 8 * kq;
+            int ci = k / ks2, kk = k - ci * ks2;   // divisions by constants when KS > 0
+            int ky = kk / ks, kx = kk - ky * ks;
+            u16x8 v8;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                bf16b v = 0;
+                if (pix && k < K) {
+                    const int y = ypix + ky - pad, x = xpix + kx - pad;
+                    if ((unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W) {
+                        const size_t off = (size_t)ci * HW + (size_t)y * a.W + x;
+                        v = inb[off];
+                        if (mb && !(b2f(mb[off]) > 0.0f)) v = 0;
+                    }
+                }
+                v8[t] = v;
+                ++k;
+                if (++kx == ks) {
+                    kx = 0;
+                    if (++ky == ks) {
+                        ky = 0;
+                        ++ci;
+                    }
                 }
             }
-            sB[pr * kLdsK + c] = v;
+            *(u16x8 *)(sB + pr * kLdsK + 8 * kq) = v8;
         }
         __syncthreads();
         bf16x8_t fa[2], fb[2];
@@ -104,10 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
 // g[co][p] * (mask>0) * col[k][p]; all images of the batch are one pixel axis
 // ---------------------------------------------------------------------------
 
+template <int KS>
 __global__ __launch_bounds__(kBlock) void k_conv_wgrad(ConvWgrad a) {
+    static_assert(kBlock % kKC == 0 && kT % (kBlock / kKC) == 0, "whole rows per staging pass");
     __shared__ __attribute__((aligned(16))) bf16b sA[kT * kLdsK];   // [co][p]
     __shared__ __attribute__((aligned(16))) bf16b sB[kT * kLdsK];   // [k][p]
-    const int HW = a.H * a.W, K = a.Cin * a.ks * a.ks, ks2 = a.ks * a.ks, pad = a.ks / 2;
+    const int ks = KS > 0 ? KS : a.ks, ks2 = ks * ks, pad = ks / 2;
+    const int HW = a.H * a.W, K = a.Cin * ks2;
     const long long P = (long long)a.n * HW;
     const int k0 = blockIdx.x * kT, co0 = blockIdx.y * kT, split = blockIdx.z;
     const long long per = ((P + a.nsplit - 1) / a.nsplit + kKC - 1) / kKC * kKC;
@@ -118,33 +142,48 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(ConvWgrad a) {
     f4_t acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = (f4_t){0.0f, 0.0f, 0.0f, 0.0f};
+    // staging: the thread's pixel column cB of each chunk, rows rB, rB + 8, ...
+    // of both tiles; the pixel's image, row and column are found once and
+    // advanced by kKC pixels per chunk
+    const int cB = threadIdx.x % kKC, rB = threadIdx.x / kKC;
+    int img = 0, yy = 0, xx = 0;
+    if (pb + cB < P) {
+        img = (int)((pb + cB) / HW);
+        const int p = (int)(pb + cB - (long long)img * HW);
+        yy = p / a.W;
+        xx = p - yy * a.W;
+    }
     for (long long pc = pb; pc < pe; pc += kKC) {
-        for (int e = threadIdx.x; e < kT * kKC; e += kBlock) {
-            const int r = e / kKC, c = e - r * kKC;
+        const bool live = pc + cB < pe;
+        const int p = yy * a.W + xx;
+        for (int r = rB; r < kT; r += kBlock / kKC) {
             const int co = co0 + r;
-            const long long pp = pc + c;
             bf16b v = 0;
-            if (co < a.Cout && pp < pe) {
-                const int img = (int)(pp / HW), p = (int)(pp - (long long)img * HW);
+            if (co < a.Cout && live) {
                 v = a.g[((size_t)img * a.g_ct + a.g_c0 + co) * HW + p];
                 if (a.mask && !(b2f(a.mask[((size_t)img * a.mask_ct + a.mask_c0 + co) * HW + p]) > 0.0f)) v = 0;
             }
-            sA[r * kLdsK + c] = v;
+            sA[r * kLdsK + cB] = v;
         }
-        for (int e = threadIdx.x; e < kT * kKC; e += kBlock) {
-            const int r = e / kKC, c = e - r * kKC;
+        for (int r = rB; r < kT; r += kBlock / kKC) {
             const int k = k0 + r;
-            const long long pp = pc + c;
             bf16b v = 0;
-            if (k < K && pp < pe) {
-                const int img = (int)(pp / HW), p = (int)(pp - (long long)img * HW);
-                const int ci = k / ks2, kk = k - ci * ks2;
-                const int ky = kk / a.ks, kx = kk - ky * a.ks;
-                const int y = p / a.W + ky - pad, x = p % a.W + kx - pad;
+            if (k < K && live) {
+                const int ci = k / ks2, kk = k - ci * ks2;   // divisions by constants when KS > 0
+                const int ky = kk / ks, kx = kk - ky * ks;
+                const int y = yy + ky - pad, x = xx + kx - pad;
                 if ((unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W)
                     v = a.in[((size_t)img * a.in_ct + a.in_c0 + ci) * HW + (size_t)y * a.W + x];
             }
-            sB[r * kLdsK + c] = v;
+            sB[r * kLdsK + cB] = v;
+        }
+        xx += kKC;   // the next chunk's pixel
+        while (xx >= a.W) {
+            xx -= a.W;
+            if (++yy == a.H) {
+                yy = 0;
+                ++img;
+            }
         }
         __syncthreads();
         bf16x8_t fa[2], fb[2];
@@ -378,12 +417,16 @@ static int eblocks(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>(
 // ---- launchers used by the host-side network
 void cnn_conv_fwd(const ConvFwd &a, hipStream_t st) {
     dim3 grid((a.H * a.W + kT - 1) / kT, (a.Cout + kT - 1) / kT, a.n);
-    k_conv_fwd<<<grid, kBlock, 0, st>>>(a);
+    if (a.ks == 3) k_conv_fwd<3><<<grid, kBlock, 0, st>>>(a);
+    else if (a.ks == 1) k_conv_fwd<1><<<grid, kBlock, 0, st>>>(a);
+    else k_conv_fwd<0><<<grid, kBlock, 0, st>>>(a);
 }
 void cnn_conv_wgrad(const ConvWgrad &a, hipStream_t st) {
     const int K = a.Cin * a.ks * a.ks;
     dim3 grid((K + kT - 1) / kT, (a.Cout + kT - 1) / kT, a.nsplit);
-    k_conv_wgrad<<<grid, kBlock, 0, st>>>(a);
+    if (a.ks == 3) k_conv_wgrad<3><<<grid, kBlock, 0, st>>>(a);
+    else if (a.ks == 1) k_conv_wgrad<1><<<grid, kBlock, 0, st>>>(a);
+    else k_conv_wgrad<0><<<grid, kBlock, 0, st>>>(a);
 }
 void cnn_wgrad_reduce(const float *partial, int nsplit, size_t n, float *gw, hipStream_t st) {
     k_wgrad_reduce<<<eblocks(n), kBlock, 0, st>>>(partial, nsplit, n, gw);
