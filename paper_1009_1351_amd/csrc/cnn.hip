@@ -212,20 +212,33 @@ __global__ void k_wgrad_reduce(const float *__restrict__ partial, int nsplit, si
     }
 }
 
+// bias gradient in two steps: part[co][img * nsp + sp] = sum over the pixel
+// range sp of image img of the masked output gradient (one block each), then
+// gb[co] = the sum of the co's partials in order (deterministic)
 __global__ __launch_bounds__(kBlock) void k_bias_grad(const bf16b *__restrict__ g, int g_c0, int g_ct,
-                                                      const bf16b *__restrict__ mask, int mask_c0, int mask_ct, int n,
-                                                      int HW, float *__restrict__ gb) {
+                                                      const bf16b *__restrict__ mask, int mask_c0, int mask_ct,
+                                                      int HW, int nsp, double *__restrict__ part) {
     __shared__ double sh[kBlock];
-    const int co = blockIdx.x;
+    const int co = blockIdx.x, img = blockIdx.y / nsp, sp = blockIdx.y - img * nsp;
+    const int per = (HW + nsp - 1) / nsp, pbeg = sp * per, pend = min(HW, pbeg + per);
+    const bf16b *gr = g + ((size_t)img * g_ct + g_c0 + co) * HW;
+    const bf16b *mr = mask ? mask + ((size_t)img * mask_ct + mask_c0 + co) * HW : nullptr;
     double s = 0.0;
-    for (int img = 0; img < n; ++img)
-        for (int p = threadIdx.x; p < HW; p += kBlock) {
-            float v = b2f(g[((size_t)img * g_ct + g_c0 + co) * HW + p]);
-            if (mask && !(b2f(mask[((size_t)img * mask_ct + mask_c0 + co) * HW + p]) > 0.0f)) v = 0.0f;
-            s += v;
-        }
+    for (int p = pbeg + threadIdx.x; p < pend; p += kBlock) {
+        float v = b2f(gr[p]);
+        if (mr && !(b2f(mr[p]) > 0.0f)) v = 0.0f;
+        s += v;
+    }
     s = block_sum_256(s, sh);
-    if (threadIdx.x == 0) gb[co] = (float)s;
+    if (threadIdx.x == 0) part[(size_t)co * gridDim.y + blockIdx.y] = s;
+}
+
+__global__ void k_bias_reduce(const double *__restrict__ part, int nper, int Cout, float *__restrict__ gb) {
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co >= Cout) return;
+    double s = 0.0;
+    for (int k = 0; k < nper; ++k) s += part[(size_t)co * nper + k];
+    gb[co] = (float)s;
 }
 
 // W'[ci][co][ks-1-ky][ks-1-kx] = W[co][ci][ky][kx]
@@ -431,9 +444,18 @@ void cnn_conv_wgrad(const ConvWgrad &a, hipStream_t st) {
 void cnn_wgrad_reduce(const float *partial, int nsplit, size_t n, float *gw, hipStream_t st) {
     k_wgrad_reduce<<<eblocks(n), kBlock, 0, st>>>(partial, nsplit, n, gw);
 }
+int cnn_bias_splits(int n, int HW, int Cout) {
+    // about 2048 blocks, at least 1024 pixels each, at most kBiasPartials partials
+    int nsp = std::max(1, 2048 / std::max(1, Cout * n));
+    nsp = std::min(nsp, std::max(1, HW / 1024));
+    nsp = std::min(nsp, std::max(1, kBiasPartials / std::max(1, Cout * n)));
+    return nsp;
+}
 void cnn_bias_grad(const bf16b *g, int g_c0, int g_ct, const bf16b *mask, int mask_c0, int mask_ct, int n, int HW,
-                   int Cout, float *gb, hipStream_t st) {
-    k_bias_grad<<<Cout, kBlock, 0, st>>>(g, g_c0, g_ct, mask, mask_c0, mask_ct, n, HW, gb);
+                   int Cout, double *part, float *gb, hipStream_t st) {
+    const int nsp = cnn_bias_splits(n, HW, Cout);
+    k_bias_grad<<<dim3(Cout, n * nsp), kBlock, 0, st>>>(g, g_c0, g_ct, mask, mask_c0, mask_ct, HW, nsp, part);
+    k_bias_reduce<<<(Cout + kBlock - 1) / kBlock, kBlock, 0, st>>>(part, n * nsp, Cout, gb);
 }
 void cnn_flip(const bf16b *w, bf16b *wt, int Cout, int Cin, int ks, hipStream_t st) {
     k_flip_weights<<<eblocks((size_t)Cout * Cin * ks * ks), kBlock, 0, st>>>(w, wt, Cout, Cin, ks);

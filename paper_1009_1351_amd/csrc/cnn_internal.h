@@ -38,8 +38,11 @@ struct ConvWgrad {
 void cnn_conv_fwd(const ConvFwd &a, hipStream_t st);
 void cnn_conv_wgrad(const ConvWgrad &a, hipStream_t st);
 void cnn_wgrad_reduce(const float *partial, int nsplit, size_t n, float *gw, hipStream_t st);
+// bias gradient; part: device scratch of at least kBiasPartials doubles
+constexpr int kBiasPartials = 8192;
+int cnn_bias_splits(int n, int HW, int Cout);
 void cnn_bias_grad(const bf16b *g, int g_c0, int g_ct, const bf16b *mask, int mask_c0, int mask_ct, int n, int HW,
-                   int Cout, float *gb, hipStream_t st);
+                   int Cout, double *part, float *gb, hipStream_t st);
 void cnn_flip(const bf16b *w, bf16b *wt, int Cout, int Cin, int ks, hipStream_t st);
 void cnn_to_bf16(const float *x, float s, bf16b *y, size_t n, hipStream_t st);
 void cnn_pool_fwd(const bf16b *src, int c0, int ct, bf16b *dst, int n, int C, int H, int W, hipStream_t st);

@@ -59,6 +59,7 @@ struct tnlm_cnn {
     float *part = nullptr;
     size_t part_cap = 0;
     double *lpart = nullptr;
+    double *bpart = nullptr;   // bias-gradient partials (kBiasPartials)
     int *flag = nullptr;
     long long step = 0;
     // activations for the current (n, H, W)
@@ -74,7 +75,7 @@ struct tnlm_cnn {
         (void)hipStreamSynchronize(stream);
         free_acts();
         for (void *p : {(void *)Pm, (void *)G, (void *)M, (void *)V, (void *)Wb, (void *)Wt, (void *)part, (void *)lpart,
-                        (void *)flag, (void *)rs})
+                        (void *)bpart, (void *)flag, (void *)rs})
             if (p) (void)hipFree(p);
     }
     void free_acts() {
@@ -231,9 +232,10 @@ static void forward(tnlm_cnn &c, const float *xin, int n, int H, int W) {
 static int nsplit_for(const CnnLayer &l, long long P) {
     const int K = l.Cin * l.ks * l.ks;
     const int tiles = ((K + 63) / 64) * ((l.Cout + 63) / 64);
-    int ns = std::max(1, 512 / tiles);
+    // about 8 blocks per CU (256 CUs), at least 8 pixel chunks of 32 per split
+    int ns = std::max(1, 2048 / tiles);
     ns = (int)std::min<long long>(ns, std::max<long long>(1, P / 256));
-    return std::min(ns, 64);
+    return std::min(ns, 256);
 }
 
 // one layer's backward: gW, gb into c.G; input gradient into gin (if gin.p)
@@ -270,7 +272,7 @@ static tnlm_status layer_bwd(tnlm_cnn &c, int li, TRef g, TRef mask, TRef in, TR
     wa.nsplit = ns;
     cnn_conv_wgrad(wa, st);
     cnn_wgrad_reduce(c.part, ns, (size_t)l.Cout * K, c.G + l.w_off, st);
-    cnn_bias_grad(g.p, g.c0, g.ct, mask.p, mask.c0, mask.ct, n, H * W, l.Cout, c.G + l.b_off, st);
+    cnn_bias_grad(g.p, g.c0, g.ct, mask.p, mask.c0, mask.ct, n, H * W, l.Cout, c.bpart, c.G + l.b_off, st);
     if (gin.p) {
         cnn_flip(c.Wb + l.w_off, c.Wt, l.Cout, l.Cin, l.ks, st);
         ConvFwd a{};
@@ -402,6 +404,7 @@ tnlm_status tnlm_cnn_create(tnlm_cnn **out, int32_t phases, int32_t base_channel
     CHIP(hipMalloc(&c->Wb, c->nweights * sizeof(bf16b)));
     CHIP(hipMalloc(&c->Wt, maxw * sizeof(bf16b)));
     CHIP(hipMalloc(&c->lpart, 1024 * sizeof(double)));
+    CHIP(hipMalloc(&c->bpart, kBiasPartials * sizeof(double)));
     CHIP(hipMalloc(&c->flag, sizeof(int)));
     CHIP(hipMemcpy(c->Pm, h.data(), c->nparams * sizeof(float), hipMemcpyHostToDevice));
     cnn_fill_f32(c->M, c->nparams, 0.0f, c->stream);
