@@ -35,9 +35,12 @@ constexpr int kLdsK = 40;  // padded K stride in LDS (elements): 80 bytes, 16-by
 // ---------------------------------------------------------------------------
 
 // KS: the kernel size when known at compile time (1 or 3), 0 for any (a.ks).
+// Each chunk's operands are loaded into registers one chunk ahead (issued
+// before the current chunk's matrix operations), then stored to LDS.
 template <int KS>
 __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
     static_assert(kT == 64 && kBlock == 4 * kT && kKC == 32, "one pixel and 8 K-values per thread in staging");
+    static_assert(kT * kKC == 8 * kBlock, "8 weight values per thread in staging");
     __shared__ __attribute__((aligned(16))) bf16b sA[kT * kLdsK];
     __shared__ __attribute__((aligned(16))) bf16b sB[kT * kLdsK];
     const int ks = KS > 0 ? KS : a.ks, ks2 = ks * ks, pad = ks / 2;
@@ -51,24 +54,54 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
         for (int j = 0; j < 2; ++j) acc[i][j] = (f4_t){0.0f, 0.0f, 0.0f, 0.0f};
     const bf16b *inb = a.in + ((size_t)nimg * a.in_ct + a.in_c0) * HW;
     const bf16b *mb = a.mask ? a.mask + ((size_t)nimg * a.mask_ct + a.mask_c0) * HW : nullptr;
-    // im2col staging: pixel p0 + pr and K-values [8 kq, 8 kq + 8) of each chunk
-    const int pr = threadIdx.x & (kT - 1), kq = threadIdx.x >> 6;
+    // weight staging: element e = threadIdx.x + kBlock j of the chunk, row e / kKC, column e % kKC
+    const int ar = threadIdx.x / kKC, ac = threadIdx.x % kKC;   // rows ar + (kBlock / kKC) j
+    // im2col staging: pixel p0 + pr and K-values [8 kq, 8 kq + 8) of each chunk;
+    // kq is the wave's index, so the K-values' (ci, ky, kx) are the same for
+    // the whole wave (scalar registers) and a lane only tests its pixel's
+    // neighbour mask (bit ky * ks + kx: neighbour inside the image)
+    const int pr = threadIdx.x & (kT - 1), kq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool pix = p0 + pr < HW;
     const int ypix = pix ? (p0 + pr) / a.W : 0, xpix = pix ? p0 + pr - ypix * a.W : 0;
-    for (int kc = 0; kc < K; kc += kKC) {
-        // A: weights rows co0.., K columns kc..
-        for (int e = threadIdx.x; e < kT * kKC; e += kBlock) {
-            const int r = e / kKC, c = e - r * kKC;
-            const int co = co0 + r, k = kc + c;
-            sA[r * kLdsK + c] = (co < a.Cout && k < K) ? a.w[(size_t)co * K + k] : (bf16b)0;
+    const int pixoff = ypix * a.W + xpix;
+    unsigned nbr = 0;
+    if (KS > 0 && pix) {
+#pragma unroll
+        for (int ky = 0; ky < KS; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < KS; ++kx)
+                if ((unsigned)(ypix + ky - pad) < (unsigned)a.H && (unsigned)(xpix + kx - pad) < (unsigned)a.W)
+                    nbr |= 1u << (ky * KS + kx);
+    }
+    auto load_chunk = [&](int kc, u16x8 &av, u16x8 &bv) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {   // A: weights rows co0.., K columns kc..
+            const int co = co0 + ar + (kBlock / kKC) * j, k = kc + ac;
+            av[j] = (co < a.Cout && k < K) ? a.w[(size_t)co * K + k] : (bf16b)0;
         }
         // B: im2col, stored [pixel][k]; the thread's 8 K-values of its pixel
-        // (consecutive lanes on consecutive pixels), written as one 16-byte store
-        {
-            int k = kc + 8 * kq;
-            int ci = k / ks2, kk = k - ci * ks2;   // divisions by constants when KS > 0
+        // (consecutive lanes on consecutive pixels)
+        int k = kc + 8 * kq;
+        if constexpr (KS > 0) {
+            int ci = k / (KS * KS), kk = k - ci * (KS * KS);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int ky = kk / KS, kx = kk - ky * KS;
+                const bool ok = k < K && ((nbr >> kk) & 1u) != 0;
+                // a lane without the value reads the tensor's first element instead
+                const int off = ok ? ci * HW + pixoff + (ky - pad) * a.W + (kx - pad) : 0;
+                bf16b v = inb[off];
+                if (mb && !(b2f(mb[off]) > 0.0f)) v = 0;
+                bv[t] = ok ? v : (bf16b)0;
+                ++k;
+                if (++kk == KS * KS) {
+                    kk = 0;
+                    ++ci;
+                }
+            }
+        } else {
+            int ci = k / ks2, kk = k - ci * ks2;
             int ky = kk / ks, kx = kk - ky * ks;
-            u16x8 v8;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 bf16b v = 0;
@@ -80,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
                         if (mb && !(b2f(mb[off]) > 0.0f)) v = 0;
                     }
                 }
-                v8[t] = v;
+                bv[t] = v;
                 ++k;
                 if (++kx == ks) {
                     kx = 0;
@@ -90,9 +123,16 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(ConvFwd a) {
                     }
                 }
             }
-            *(u16x8 *)(sB + pr * kLdsK + 8 * kq) = v8;
         }
+    };
+    u16x8 av, bv;
+    load_chunk(0, av, bv);
+    for (int kc = 0; kc < K; kc += kKC) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[(ar + (kBlock / kKC) * j) * kLdsK + ac] = av[j];
+        *(u16x8 *)(sB + pr * kLdsK + 8 * kq) = bv;
         __syncthreads();
+        if (kc + kKC < K) load_chunk(kc + kKC, av, bv);   // in flight during this chunk's products
         bf16x8_t fa[2], fb[2];
         for (int i = 0; i < 2; ++i) {
             const u16x8 va = *(const u16x8 *)(sA + (wm * 32 + i * 16 + l16) * kLdsK + 8 * kg);
