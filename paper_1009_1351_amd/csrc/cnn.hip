@@ -193,20 +193,23 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(ConvWgrad a) {
         yy = p / a.W;
         xx = p - yy * a.W;
     }
-    for (long long pc = pb; pc < pe; pc += kKC) {
+    // one chunk's operands into registers, then the pixel advanced by kKC
+    auto load_chunk = [&](long long pc, u16x8 &av, u16x8 &bv) {
         const bool live = pc + cB < pe;
         const int p = yy * a.W + xx;
-        for (int r = rB; r < kT; r += kBlock / kKC) {
-            const int co = co0 + r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int co = co0 + rB + (kBlock / kKC) * j;
             bf16b v = 0;
             if (co < a.Cout && live) {
                 v = a.g[((size_t)img * a.g_ct + a.g_c0 + co) * HW + p];
                 if (a.mask && !(b2f(a.mask[((size_t)img * a.mask_ct + a.mask_c0 + co) * HW + p]) > 0.0f)) v = 0;
             }
-            sA[r * kLdsK + cB] = v;
+            av[j] = v;
         }
-        for (int r = rB; r < kT; r += kBlock / kKC) {
-            const int k = k0 + r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + rB + (kBlock / kKC) * j;
             bf16b v = 0;
             if (k < K && live) {
                 const int ci = k / ks2, kk = k - ci * ks2;   // divisions by constants when KS > 0
@@ -215,9 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(ConvWgrad a) {
                 if ((unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W)
                     v = a.in[((size_t)img * a.in_ct + a.in_c0 + ci) * HW + (size_t)y * a.W + x];
             }
-            sB[r * kLdsK + cB] = v;
+            bv[j] = v;
         }
-        xx += kKC;   // the next chunk's pixel
+        xx += kKC;
         while (xx >= a.W) {
             xx -= a.W;
             if (++yy == a.H) {
@@ -225,7 +228,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(ConvWgrad a) {
                 ++img;
             }
         }
+    };
+    static_assert(kT == 8 * (kBlock / kKC), "8 rows of each tile per thread");
+    u16x8 av, bv;
+    if (pb < pe) load_chunk(pb, av, bv);
+    for (long long pc = pb; pc < pe; pc += kKC) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sA[(rB + (kBlock / kKC) * j) * kLdsK + cB] = av[j];
+            sB[(rB + (kBlock / kKC) * j) * kLdsK + cB] = bv[j];
+        }
         __syncthreads();
+        if (pc + kKC < pe) load_chunk(pc + kKC, av, bv);   // in flight during this chunk's products
         bf16x8_t fa[2], fb[2];
         for (int i = 0; i < 2; ++i) {
             fa[i] = __builtin_bit_cast(bf16x8_t, *(const u16x8 *)(sA + (wm * 32 + i * 16 + l16) * kLdsK + 8 * kg));
