@@ -580,7 +580,10 @@ __device__ __forceinline__ void bp_block_ray(const float4 A, const float qb, flo
     const float X0 = fmaf(fc0, A.x, A.y), X1 = fmaf(fc1, A.x, A.y), X2 = fmaf(fc2, A.x, A.y);
     const float Y0 = fmaf(fr0, A.z, A.w), Y1 = fmaf(fr1, A.z, A.w), Y2 = fmaf(fr2, A.z, A.w);
     const float tin = fmaxf(XP ? X0 : X2, YP ? Y0 : Y2);
-    const float tout = fmaxf(fminf(XP ? X2 : X0, YP ? Y2 : Y0), tin);   // tin when the ray misses the square
+    // max(min(exit planes), tin), which is tin when the ray misses the square:
+    // the median of the three, since each entry plane lies at or before its
+    // exit plane and so tin is at most the larger exit plane
+    const float tout = __builtin_amdgcn_fmed3f(XP ? X2 : X0, YP ? Y2 : Y0, tin);
     const float x1 = __builtin_amdgcn_fmed3f(tin, X1, tout);
     const float y1 = __builtin_amdgcn_fmed3f(tin, Y1, tout);
     const float a = fminf(x1, y1), b = fmaxf(x1, y1);
