@@ -499,11 +499,9 @@ void cnn_wgrad_reduce(const float *partial, int nsplit, size_t n, float *gw, hip
     k_wgrad_reduce<<<eblocks(n), kBlock, 0, st>>>(partial, nsplit, n, gw);
 }
 int cnn_bias_splits(int n, int HW, int Cout) {
-    // about 2048 blocks, at least 1024 pixels each, at most kBiasPartials partials
+    // pixel ranges per image: about 2048 blocks in all, at least 1024 pixels each
     int nsp = std::max(1, 2048 / std::max(1, Cout * n));
-    nsp = std::min(nsp, std::max(1, HW / 1024));
-    nsp = std::min(nsp, std::max(1, kBiasPartials / std::max(1, Cout * n)));
-    return nsp;
+    return std::min(nsp, std::max(1, HW / 1024));
 }
 void cnn_bias_grad(const bf16b *g, int g_c0, int g_ct, const bf16b *mask, int mask_c0, int mask_ct, int n, int HW,
                    int Cout, double *part, float *gb, hipStream_t st) {

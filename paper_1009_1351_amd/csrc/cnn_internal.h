@@ -38,8 +38,7 @@ struct ConvWgrad {
 void cnn_conv_fwd(const ConvFwd &a, hipStream_t st);
 void cnn_conv_wgrad(const ConvWgrad &a, hipStream_t st);
 void cnn_wgrad_reduce(const float *partial, int nsplit, size_t n, float *gw, hipStream_t st);
-// bias gradient; part: device scratch of at least kBiasPartials doubles
-constexpr int kBiasPartials = 8192;
+// bias gradient; part: device scratch of Cout * n * cnn_bias_splits(n, HW, Cout) doubles
 int cnn_bias_splits(int n, int HW, int Cout);
 void cnn_bias_grad(const bf16b *g, int g_c0, int g_ct, const bf16b *mask, int mask_c0, int mask_ct, int n, int HW,
                    int Cout, double *part, float *gb, hipStream_t st);

@@ -59,7 +59,8 @@ struct tnlm_cnn {
     float *part = nullptr;
     size_t part_cap = 0;
     double *lpart = nullptr;
-    double *bpart = nullptr;   // bias-gradient partials (kBiasPartials)
+    double *bpart = nullptr;   // bias-gradient partials
+    size_t bpart_cap = 0;
     int *flag = nullptr;
     long long step = 0;
     // activations for the current (n, H, W)
@@ -272,6 +273,13 @@ static tnlm_status layer_bwd(tnlm_cnn &c, int li, TRef g, TRef mask, TRef in, TR
     wa.nsplit = ns;
     cnn_conv_wgrad(wa, st);
     cnn_wgrad_reduce(c.part, ns, (size_t)l.Cout * K, c.G + l.w_off, st);
+    const size_t bneed = (size_t)l.Cout * n * cnn_bias_splits(n, H * W, l.Cout);
+    if (bneed > c.bpart_cap) {
+        if (c.bpart) CHIP(hipFree(c.bpart));
+        c.bpart = nullptr;
+        CHIP(hipMalloc(&c.bpart, bneed * sizeof(double)));
+        c.bpart_cap = bneed;
+    }
     cnn_bias_grad(g.p, g.c0, g.ct, mask.p, mask.c0, mask.ct, n, H * W, l.Cout, c.bpart, c.G + l.b_off, st);
     if (gin.p) {
         cnn_flip(c.Wb + l.w_off, c.Wt, l.Cout, l.Cin, l.ks, st);
@@ -404,7 +412,6 @@ tnlm_status tnlm_cnn_create(tnlm_cnn **out, int32_t phases, int32_t base_channel
     CHIP(hipMalloc(&c->Wb, c->nweights * sizeof(bf16b)));
     CHIP(hipMalloc(&c->Wt, maxw * sizeof(bf16b)));
     CHIP(hipMalloc(&c->lpart, 1024 * sizeof(double)));
-    CHIP(hipMalloc(&c->bpart, kBiasPartials * sizeof(double)));
     CHIP(hipMalloc(&c->flag, sizeof(int)));
     CHIP(hipMemcpy(c->Pm, h.data(), c->nparams * sizeof(float), hipMemcpyHostToDevice));
     cnn_fill_f32(c->M, c->nparams, 0.0f, c->stream);

@@ -59,6 +59,43 @@ def test_gradients_match_fp64_reference(P, b, H, n):
     assert rel(g[-nb:].astype(np.float64), gref[-nb:]) < 1e-3
 
 
+def test_large_batch_gradient_is_mean_of_sub_batches():
+    """64 images in one batch against the same images in 8 batches of 8. A
+    per-image forward and backward does not depend on the batch, and the
+    output gradient 2 d / count is scaled by exactly 1/8 (BF16 storage
+    included), so the two differ only in the FP32 order of the weight- and
+    bias-gradient sums over pixels and images (split partials, reduced in a
+    fixed order). The batch needs 256 channels x 64 images of bias-gradient
+    partials at the deepest level. The FP64 reference cannot judge this shape:
+    at 8 x 8 with BF16 activations its own gradients move by ~5e-3 when the
+    input moves by 1e-7 (activation roundings flip)."""
+    P, b, H, n, m = 10, 32, 8, 64, 8
+    nt = net(P, b, seed=5)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 0.03, size=(n, P, H, H)).astype(np.float32)
+    t = (x + rng.normal(0, 0.002, size=x.shape)).astype(np.float32)
+    loss, g = nt.loss_grad(to_dev(x).reshape(n, P, H, H), to_dev(t).reshape(n, P, H, H))
+    acc = np.zeros(g.size, np.float64)
+    losses = []
+    for k in range(n // m):
+        sl = slice(k * m, (k + 1) * m)
+        lk, gk = nt.loss_grad(to_dev(x[sl]).reshape(m, P, H, H), to_dev(t[sl]).reshape(m, P, H, H))
+        acc += gk.astype(np.float64) / (n // m)
+        losses.append(lk)
+    from oracle import cnn_ref
+    errs, off = [], 0
+    for ci, co, k, _ in cnn_ref.layers(P, b):
+        sz = co * ci * k * k
+        errs.append(rel(g[off:off + sz].astype(np.float64), acc[off:off + sz]))
+        off += sz
+    nb = sum(co for _, co, _, _ in cnn_ref.layers(P, b))
+    eb = rel(g[-nb:].astype(np.float64), acc[-nb:])
+    announce(f"batch 64 vs 8 x 8: loss {loss:.6e} / {np.mean(losses):.6e}; weight-gradient rel per layer max "
+             f"{max(errs):.1e}, bias {eb:.1e}")
+    assert abs(loss - np.mean(losses)) <= 1e-6 * abs(loss)
+    assert max(errs) < 1e-4 and eb < 1e-4
+
+
 def test_first_adam_step_matches_closed_form():
     # at step 1 the bias-corrected moments are g and g^2, so Adam moves each
     # parameter by lr * g / (|g| + eps)
