@@ -940,11 +940,15 @@ void launch_regularize_sym(const Batch &b, const Stage &st, const RegParams &p, 
     f.clamp = clamp;
     f.relpart = relpart;
     f.nonfinite = nonfinite;
+    // the combining pass streams through its tiles: the fixed per-XCD ranges,
+    // without the work counters (one atomic round trip per tile)
+    Stage fs = st;
+    fs.queue = nullptr;
     switch (p.patch / 2) {
-        case 1: k_tnlm_sym_finish<1, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
-        case 2: k_tnlm_sym_finish<2, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
-        case 3: k_tnlm_sym_finish<3, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
-        default: k_tnlm_sym_finish<4, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, st, f); break;
+        case 1: k_tnlm_sym_finish<1, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, fs, f); break;
+        case 2: k_tnlm_sym_finish<2, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, fs, f); break;
+        case 3: k_tnlm_sym_finish<3, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, fs, f); break;
+        default: k_tnlm_sym_finish<4, kSymBY><<<st.grid, kBlock, 0, strm>>>(b, fs, f); break;
     }
 }
 
