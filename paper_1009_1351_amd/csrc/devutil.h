@@ -6,17 +6,19 @@ namespace tnlm {
 
 constexpr int kBlock = 256;
 
-// Sum of one double per thread over a 256-thread block, fixed tree order.
-// Every thread returns the total. Uses 256 doubles of shared memory.
+// Sum of one double per thread over a 256-thread block, in a fixed order.
+// Every thread returns the total; all threads must call it. Uses the first 4
+// doubles of sh.
 __device__ inline double block_sum_256(double v, double *sh) {
+    static_assert(kBlock == 256, "four waves");
+    // butterfly within the wave: both lanes of a pair form the same sum, so
+    // every lane ends with the same value, in a fixed order; then the four
+    // waves' sums in a fixed order
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
     const int t = threadIdx.x + threadIdx.y * blockDim.x;
-    sh[t] = v;
+    if ((t & 63) == 0) sh[t >> 6] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) sh[t] += sh[t + s];
-        __syncthreads();
-    }
-    double r = sh[0];
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     __syncthreads();
     return r;
 }
