@@ -66,7 +66,7 @@ def test_large_batch_gradient_is_mean_of_sub_batches():
     included), so the two differ only in the FP32 order of the weight- and
     bias-gradient sums over pixels and images (split partials, reduced in a
     fixed order). The batch needs 256 channels x 64 images of bias-gradient
-    partials at the deepest level. The FP64 reference cannot judge this shape:
+    partials at the deepest level. The FP64 reference cannot settle this shape:
     at 8 x 8 with BF16 activations its own gradients move by ~5e-3 when the
     input moves by 1e-7 (activation roundings flip)."""
     P, b, H, n, m = 10, 32, 8, 64, 8
@@ -175,7 +175,7 @@ def test_warm_start_pipeline_small(orc):
         assert st == 0 and r < 1e-3
         if f_first is None:
             f_first, k_first = f, k
-    # the oracle judges the final image of the learned path: its own solve of
+    # the oracle checks the final image of the learned path: its own solve of
     # the first slice from the cold start to the same tolerance. Both stop at
     # a relative update below 1e-3 of a contraction (about 0.9 per iteration
     # at this size), so each is within ~1e-2 of the fixed point.

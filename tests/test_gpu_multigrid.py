@@ -50,7 +50,7 @@ def test_two_level_solve_reaches_the_cold_solution():
 
 
 def test_two_level_solve_matches_oracle_solve():
-    """The oracle judges the coarse-to-fine path: its own cold solve of the
+    """The oracle checks the coarse-to-fine path: its own cold solve of the
     64^2 workload to the same relative-update tolerance (stored by
     tests/golden/make_golden.py as c1tol). Both stop where the
     update falls below tol; with the contraction rho of the outer iteration
