@@ -65,7 +65,7 @@ struct Engine {
     std::vector<void *> allocs;
     Batch batch{};
     SliceDesc *d_sl = nullptr;
-    float4 *rt0 = nullptr, *rt1 = nullptr, *vt = nullptr;
+    float4 *rt0 = nullptr, *vt = nullptr;
     int4 *vo = nullptr;
     float *hfilt = nullptr, *cw = nullptr;
     Stage st_fp{}, st_bp{}, st_vec{}, st_reg{}, st_ffilt{}, st_fbp_all{}, st_fbp_ph{}, st_tr{};
@@ -227,9 +227,8 @@ static tnlm_status validate_params(const tnlm_params *p, int minL) {
 // Per-ray plane tables in double precision, rounded once to float.
 // crossings receives the slice's ray-pixel crossings (|dc| + |dr| + 1 cells
 // per ray that meets the image), the cost of one forward projection.
-static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &rt1,
-                          std::vector<float4> &vt, std::vector<int4> &vo, std::vector<float> &hf,
-                          std::vector<float> &cw, double &crossings) {
+static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std::vector<float4> &vt,
+                          std::vector<int4> &vo, std::vector<float> &hf, std::vector<float> &cw, double &crossings) {
     crossings = 0.0;
     const int N = g.n_phases, V = g.n_views, B = g.n_bins, L = g.L;
     const double D = g.pixel_mm, X0 = -0.5 * D * L;
@@ -247,7 +246,6 @@ static bool append_tables(const tnlm_geometry &g, std::vector<float4> &rt0, std:
                 const double iy = std::fabs(uy) > 1e-9 ? 1.0 / uy : std::copysign(1e9, uy == 0 ? 1.0 : uy);
                 rt0.push_back(make_float4((float)(D * ix), (float)((X0 - ox) * ix), (float)(D * iy),
                                           (float)((X0 - oy) * iy)));
-                rt1.push_back(make_float4((float)ox, (float)oy, (float)ux, (float)uy));
                 const double ax = (X0 - ox) * ix, bxp = (X0 + D * L - ox) * ix;
                 const double ay = (X0 - oy) * iy, byp = (X0 + D * L - oy) * iy;
                 const double chord = std::min(std::max(ax, bxp), std::max(ay, byp)) -
@@ -368,7 +366,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     const char *env_graph = std::getenv("TNLM_NO_GRAPH");
     E.use_graph = !(env_graph && env_graph[0] == '1');
 
-    std::vector<float4> rt0, rt1, vt;
+    std::vector<float4> rt0, vt;
     std::vector<int4> vo;
     std::vector<float> hf, cw;
     E.geoms.assign(geoms, geoms + ns);
@@ -397,7 +395,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
         d.sino0 = sino;
         d.hf0 = (int)hf.size();
         d.cw0 = (int)cw.size();
-        if (!append_tables(E.geoms[s], rt0, rt1, vt, vo, hf, cw, crossings[s]))
+        if (!append_tables(E.geoms[s], rt0, vt, vo, hf, cw, crossings[s]))
             return fail(TNLM_E_INVALID_ARG, "ray directions change sign more than once across the fan");
         d.nbp = bp_blocks(d) / d.N;
         d.npp = proj_blocks(d) / d.N;
@@ -423,13 +421,11 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     HIP_TRY(E.alloc(&E.d_sl, ns));
     HIP_TRY(hipMemcpy(E.d_sl, E.sl.data(), ns * sizeof(SliceDesc), hipMemcpyHostToDevice));
     HIP_TRY(E.alloc(&E.rt0, rt0.size()));
-    HIP_TRY(E.alloc(&E.rt1, rt1.size()));
     HIP_TRY(E.alloc(&E.vt, vt.size()));
     HIP_TRY(E.alloc(&E.vo, vo.size()));
     HIP_TRY(E.alloc(&E.hfilt, hf.size()));
     HIP_TRY(E.alloc(&E.cw, cw.size()));
     HIP_TRY(hipMemcpy(E.rt0, rt0.data(), rt0.size() * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(E.rt1, rt1.data(), rt1.size() * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.vt, vt.data(), vt.size() * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.vo, vo.data(), vo.size() * sizeof(int4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(E.hfilt, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -437,7 +433,6 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     E.batch.ns = ns;
     E.batch.sl = E.d_sl;
     E.batch.rt0 = E.rt0;
-    E.batch.rt1 = E.rt1;
     E.batch.vt = E.vt;
     E.batch.vo = E.vo;
     E.batch.skip = nullptr;

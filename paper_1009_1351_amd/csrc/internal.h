@@ -48,7 +48,6 @@ struct Batch {
     int ns = 0;
     const SliceDesc *sl = nullptr;   // device [ns]
     const float4 *rt0 = nullptr;     // rays: (Ax, Bx, Ay, By), T_x(k) = fma(k, Ax, Bx)
-    const float4 *rt1 = nullptr;     // rays: (ox, oy, ux, uy)
     const float4 *vt = nullptr;      // views: (sx, sy, cos th, sin th)
     const int4 *vo = nullptr;        // views: (bx, by, flags, 0), sign changes of Ax / Ay over the bins
     const int *skip = nullptr;       // device [ns] per-slice stop flags (nullable: run all)

@@ -470,11 +470,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (int j = 0; j < kProjRays; ++j) {
             valid[j] = b0 + j < sd.B;
             A[j] = make_float4(1.0f, 0.0f, 1.0f, 0.0f);
-            O[j] = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-            if (valid[j]) {
-                A[j] = bt.rt0[sd.ray0 + ray0 + j];
-                O[j] = bt.rt1[sd.ray0 + ray0 + j];
-            }
+            if (valid[j]) A[j] = bt.rt0[sd.ray0 + ray0 + j];
             nval += __popcll(__ballot(valid[j]));
             nxmaj += __popcll(__ballot(valid[j] && fabsf(A[j].x) < fabsf(A[j].z)));
         }
@@ -483,10 +479,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const bool tr = wave_uniform(2 * nxmaj > nval ? 1 : 0) != 0;
         if (tr) {
 #pragma unroll
-            for (int j = 0; j < kProjRays; ++j) {
-                A[j] = make_float4(A[j].z, A[j].w, A[j].x, A[j].y);
-                O[j] = make_float4(O[j].y, O[j].x, O[j].w, O[j].z);
-            }
+            for (int j = 0; j < kProjRays; ++j) A[j] = make_float4(A[j].z, A[j].w, A[j].x, A[j].y);
+        }
+        // a point of each ray and its direction, for the walk's estimates of
+        // its entry and exit cells (settled afterwards on the plane values):
+        // A.x = D / u_x and A.y = (X0 - o_x) / u_x, so u_x = D / A.x and
+        // o_x = X0 - A.y u_x (likewise in y), to a few ulp
+#pragma unroll
+        for (int j = 0; j < kProjRays; ++j) {
+            const float ux = sd.D * __builtin_amdgcn_rcpf(A[j].x), uy = sd.D * __builtin_amdgcn_rcpf(A[j].z);
+            O[j] = make_float4(fmaf(-A[j].y, ux, sd.X0), fmaf(-A[j].w, uy, sd.X0), ux, uy);
         }
         const __amdgpu_buffer_rsrc_t img = image_rsrc((tr ? fT : f) + sd.pimg0 + (long long)i * L * (L + 2), L);
         float acc[kProjRays];
