@@ -127,20 +127,31 @@ __device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stri
 // clears the counters for the next launch. Results do not depend on which
 // block takes an item. Without a queue, the fixed order of xcd_range.
 // Every thread of the block must call work_next and work_end.
+// Thread 0 asks for the item after the one it hands out at once, so that
+// the counter's reply arrives while the block works on the current item; a
+// block processes every item it obtains below the end, and the call that
+// meets the end asks for nothing more.
 struct WorkIter {
     int cur, stride, end, x;
+    int next;   // thread 0: the item already obtained for the next call (-1: none yet)
 };
 
 __device__ __forceinline__ WorkIter work_begin(const Stage &st) {
     WorkIter it;
     xcd_range(st, it.cur, it.stride, it.end);
     it.x = (int)blockIdx.x % 8;
+    it.next = -1;
     return it;
 }
 
 __device__ __forceinline__ bool work_next(const Stage &st, WorkIter &it, int &gb, int *sh_item) {
     if (st.queue && gridDim.x >= 8) {
-        if (threadIdx.x == 0) *sh_item = load_const(st.xb, it.x) + atomicAdd(st.queue + it.x, 1);
+        if (threadIdx.x == 0) {
+            const int base = load_const(st.xb, it.x);
+            const int item = it.next >= 0 ? it.next : base + atomicAdd(st.queue + it.x, 1);
+            *sh_item = item;
+            it.next = item < it.end ? base + atomicAdd(st.queue + it.x, 1) : it.end;
+        }
         __syncthreads();
         gb = *sh_item;
         __syncthreads();   // read by every thread before the next item's grab
