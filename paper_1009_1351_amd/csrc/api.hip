@@ -462,6 +462,7 @@ static tnlm_status engine_init(Engine &E, int ns, const tnlm_geometry *geoms, co
     if ((st = make_stage(E, E.st_bp, cbp, kCUs * 8, kbp)) != TNLM_OK) return st;
     E.st_fp.cu_runs = 1;
     E.st_bp.cu_runs = 1;
+    E.st_fp.prefetch = 1;   // many short items (one view's 256 rays each)
     // one set of work-item counters serves the persistent stages: their
     // launches are ordered on the engine's stream, and each launch leaves the
     // counters cleared

@@ -42,6 +42,7 @@ struct Stage {
     int grid;         // persistent grid size
     int cu_runs = 0;  // 1: blocks sharing a CU take consecutive work items
     int *queue = nullptr;   // device [9] (nullable): per-XCD item counters and a finished-block count
+    int prefetch = 0; // 1: a block asks for its next item while it works on the current one
 };
 
 struct Batch {
@@ -127,10 +128,12 @@ __device__ __forceinline__ void xcd_range(const Stage &st, int &first, int &stri
 // clears the counters for the next launch. Results do not depend on which
 // block takes an item. Without a queue, the fixed order of xcd_range.
 // Every thread of the block must call work_next and work_end.
-// Thread 0 asks for the item after the one it hands out at once, so that
-// the counter's reply arrives while the block works on the current item; a
-// block processes every item it obtains below the end, and the call that
-// meets the end asks for nothing more.
+// With st.prefetch, thread 0 asks for the item after the one it hands out at
+// once, so that the counter's reply arrives while the block works on the
+// current item; a block processes every item it obtains below the end, and
+// the call that meets the end asks for nothing more. (Each block then holds
+// two items, which widens the range an XCD's L2 serves at once: worth it for
+// many short items, not for a few long ones.)
 struct WorkIter {
     int cur, stride, end, x;
     int next;   // thread 0: the item already obtained for the next call (-1: none yet)
@@ -150,7 +153,7 @@ __device__ __forceinline__ bool work_next(const Stage &st, WorkIter &it, int &gb
             const int base = load_const(st.xb, it.x);
             const int item = it.next >= 0 ? it.next : base + atomicAdd(st.queue + it.x, 1);
             *sh_item = item;
-            it.next = item < it.end ? base + atomicAdd(st.queue + it.x, 1) : it.end;
+            if (st.prefetch) it.next = item < it.end ? base + atomicAdd(st.queue + it.x, 1) : it.end;
         }
         __syncthreads();
         gb = *sh_item;
