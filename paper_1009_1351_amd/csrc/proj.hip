@@ -639,7 +639,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     __shared__ int sh_item;
     WorkIter it = work_begin(st);
     int gb;
-    const int tx = threadIdx.x % kBpLanes, ty = threadIdx.x / kBpLanes;
+    // a wave takes an 8 x 8 square of 2 x 2 blocks (16 x 16 pixels) of the
+    // tile: its lanes' candidate bins then span the square's projected width,
+    // less on average than a 32 x 8 strip's, so each 16-byte record load of
+    // the wave touches fewer cache lines
+    static_assert(kBpLanes == 16 && kBlock == 256, "four 8 x 8 squares of lanes per tile");
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int tx = (wv & 1) * 8 + (ln & 7), ty = (wv >> 1) * 8 + (ln >> 3);
     while (work_next(st, it, gb, &sh_item)) {
         const int s = find_slice(st.pre, bt.ns, gb);
         if (bt.skip && bt.skip[s]) continue;
